@@ -1,0 +1,77 @@
+"""Pins for the oracle's preconditioned CG (no GPU): dense direct solves on tiny
+grids, the Fourier/cosine closed form for uniform coefficients, the
+mixed-precision form's residual, and the paper's qualitative claims."""
+import numpy as np
+import pytest
+
+import oracle
+import refs
+import synthetic as syn
+
+
+@pytest.mark.parametrize("coarse", ["direct", "smooth"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_matches_dense_solve(coarse, mixed):
+    rng = np.random.default_rng(41)
+    n, nz = 8, 6
+    dz = 1.05 ** np.arange(nz)
+    c = refs.random_coeffs(rng, n, nz)
+    P = oracle.Problem(c, a_h=1.0, a_z=100.0, dz=dz, levels=2, coarse=coarse)
+    b = rng.standard_normal((nz, n, n))
+    x, info = P.pcg(b, rtol=1e-14, maxit=60, mixed=mixed, flexible=mixed)
+    ref = np.linalg.solve(refs.incidence_operator(c, 1.0, 100.0, dz), b.reshape(-1))
+    err = np.linalg.norm(x.reshape(-1) - ref) / np.linalg.norm(ref)
+    assert info["converged"] and err < 1e-12, (info, err)
+
+
+def test_matches_closed_form_uniform():
+    n, nz, a_h, a_z, c0 = 64, 16, 1.0, 1e3, 1.2
+    c = np.full((3, nz, n, n), c0)
+    P = oracle.Problem(c, a_h=a_h, a_z=a_z, levels=3)
+    b = syn.normal(syn.SEED, syn.STREAM_TEST, n * n * nz).reshape(nz, n, n)
+    x, info = P.pcg(b, rtol=1e-13, maxit=60)
+    ref = refs.closed_form_solve(b, a_h, a_z, c0)
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    assert info["converged"] and err < 1e-11, (info, err)
+
+
+def test_reference_config_converges_and_beats_single_level():
+    w = syn.CONFIGS["fp64_ref_32x32x16"]
+    P = oracle.problem_for(w)
+    b = w.rhs()
+    x, info = P.pcg(b, rtol=w.rtol, maxit=100)
+    assert info["converged"] and info["true_rel_residual"] <= 1.01e-8
+    hist = info["history"]
+    assert np.all(np.diff(hist) < 0)
+    single = oracle.problem_for(w, levels=1, coarse="smooth")
+    _, info1 = single.pcg(b, rtol=w.rtol, maxit=200)
+    # Sec. 5.1: the single-level method needs several times more iterations
+    assert info1["iterations"] >= 2 * info["iterations"], (info["iterations"], info1["iterations"])
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+def test_mixed_precision_reaches_fp64_accuracy(flexible):
+    w = syn.scaled(syn.CONFIGS["fp64_512x512x64"], 64, nz=32, levels=3)
+    P = oracle.problem_for(w)
+    b = w.rhs()
+    x_ref, _ = P.pcg(b, rtol=1e-13, maxit=100)
+    x64, i64 = P.pcg(b, rtol=1e-8, maxit=100)
+    x32, i32 = P.pcg(b, rtol=1e-8, maxit=100, mixed=True, flexible=flexible)
+    assert i32["converged"] and i32["true_rel_residual"] <= 1.05e-8
+    e64 = np.linalg.norm(x64 - x_ref) / np.linalg.norm(x_ref)
+    e32 = np.linalg.norm(x32 - x_ref) / np.linalg.norm(x_ref)
+    assert e32 < 1e-7 and e64 < 1e-7, (e32, e64)
+    assert abs(i32["iterations"] - i64["iterations"]) <= 1
+
+
+def test_nonzero_initial_guess_and_zero_rhs():
+    rng = np.random.default_rng(42)
+    n, nz = 8, 4
+    c = refs.random_coeffs(rng, n, nz)
+    P = oracle.Problem(c, a_h=1.0, a_z=10.0, levels=2)
+    b = rng.standard_normal((nz, n, n))
+    x, _ = P.pcg(b, rtol=1e-12)
+    x2, info = P.pcg(b, rtol=1e-12, x0=x)
+    assert info["iterations"] <= 1
+    z, infoz = P.pcg(np.zeros_like(b), rtol=1e-8)
+    assert infoz["converged"] and infoz["iterations"] == 0 and not z.any()
