@@ -1,0 +1,212 @@
+"""Benchmark of the tensor-product multigrid hot path on one MI355X.
+
+Workload (default): periodic 1024 x 1024 columns x 128 geometrically graded
+layers (134M DOF), a_z/a_h = 1e4, c_f = 1 + 0.5 U[0,1), b ~ N(0,1), 7-level
+V-cycle (2+2 line sweeps, omega 0.8, 2 sweeps on the 16 x 16 coarsest level).
+
+One step = the whole path on that input: setup_hierarchy (coarse levels +
+FP32 copies), the mixed-precision solve to 1e-8 (FP32 V-cycle inside FP64
+CG), and the adjoint of J = 0.5 ||x||^2 (solve for lambda, then dJ/dc on
+every face).  Inputs are resident in HBM before the timed region.
+
+Beside the steps the plain FP64 solve is timed on the same input for the
+FP32-MG vs FP64 comparison, the finest-level FP32 sweep kernel is timed with
+HIP events for the roofline line, and the CPU oracle is timed on a bounded
+sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Compulsory HBM bytes per finest-level DOF (words x 4 bytes for the FP32 V-cycle):
+SWEEP_WORDS = 6            # reads u, b, c_E, c_N, c_U; writes u'
+VCYCLE_WORDS = 28.5 * 4 / 3  # 28.5 words on the finest level, times sum 4^-l
+KERNEL_SOURCES = ["paper_1605_00492_amd/csrc/tpmg_kernels.hip"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_1024x1024x128_counters.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_dof: int):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_hash() or d.get("dof") != launch_dof:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, syn):
+    """The CPU oracle (plain C, one thread) on a 1/16 column sample of the workload."""
+    import oracle
+    s = syn.scaled(w, 256, levels=5, name=f"{w.name}@256x256x{w.nz}")
+    c, b = s.coefficients(), s.rhs()
+    t0 = time.perf_counter()
+    P = oracle.problem_for(s, c)
+    x, info = P.pcg(b, rtol=s.rtol, maxit=100, mixed=True, flexible=True)
+    lam, info2 = P.pcg(x, rtol=s.rtol, maxit=100, mixed=True, flexible=True)
+    P.face_gradient(lam, x)
+    dt = time.perf_counter() - t0
+    return {"value": s.dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{s.n}x{s.n}x{s.nz} columns (1/16 of the grid), same a_z, grading, "
+                      f"coefficient law and 16x16 coarsest level; one step = setup + mixed solve "
+                      f"({info['iterations']} it) + adjoint ({info2['iterations']} it); "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="large_1024x1024x128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              f"documented but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1605_00492_amd as tp
+    import synthetic as syn
+    from paper_1605_00492_amd.binding import K_SWEEP, K_VCYCLE
+
+    w = syn.CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    log(f"generating {w.name} ({w.dof} DOF)")
+    c = torch.from_numpy(w.coefficients()).to(dev)
+    b = torch.from_numpy(w.rhs()).to(dev)
+    kw = dict(dz=w.dz(), a_h=w.a_h, a_z=w.a_z, levels=w.levels, nu=w.nu, omega=w.omega,
+              coarse=w.coarse, n_coarse=w.n_coarse)
+    torch.cuda.synchronize()
+
+    def step(record=None):
+        H = tp.Hierarchy(c, precision="mixed", **kw)
+        if record is not None:
+            H.profile_enable(True)
+        x, info = H.solve(b, rtol=w.rtol, maxit=100)
+        lam, info_adj = H.solve(x, rtol=w.rtol, maxit=100)   # dJ/dx = x for J = 0.5 ||x||^2
+        g = H.face_gradient(lam, x)
+        if record is not None:
+            record.append(dict(info=info, info_adj=info_adj,
+                               sweep=H.profile_read(K_SWEEP), vcycle=H.profile_read(K_VCYCLE)))
+        H.close()
+        return x, g
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, g = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+
+    # Instrumented step: kernel timings from HIP events on the launch stream.
+    rec = []
+    step(rec)
+    torch.cuda.synchronize()
+    r = rec[0]
+    sweep_ms, sweep_n = r["sweep"]
+    vc_ms, vc_n = r["vcycle"]
+    sweep_avg_s = sweep_ms / max(sweep_n, 1) * 1e-3
+    sweep_bytes = SWEEP_WORDS * 4 * w.dof
+    achieved = sweep_bytes / sweep_avg_s / 1e9
+    vc_avg_s = vc_ms / max(vc_n, 1) * 1e-3
+    vc_gbs = VCYCLE_WORDS * 4 * w.dof / vc_avg_s / 1e9
+
+    # Mixed vs plain FP64 solve (solve only, hierarchies already set up).
+    Hm = tp.Hierarchy(c, precision="mixed", **kw)
+    H64 = tp.Hierarchy(c, precision="fp64", **kw)
+    for H in (Hm, H64):
+        H.solve(b, rtol=w.rtol)
+    times = {}
+    sols = {}
+    for name, H in (("mixed", Hm), ("fp64", H64)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            xs, inf = H.solve(b, rtol=w.rtol)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t1) / args.steps
+        sols[name] = (xs, inf)
+    xm, im = sols["mixed"]
+    x64, i64 = sols["fp64"]
+    diff = float(torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64))
+    Hm.close()
+    H64.close()
+
+    traffic = measured_traffic(w.dof)
+    out = {
+        "metric": "time per solve to 1e-8 rel. residual (DOF/s, % HBM peak), FP32-MG vs FP64",
+        "value": w.dof / dt,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle / f64 CG",
+        "data": "synthetic (seeded SplitMix64 inputs of the stated distributions)",
+        "config": {"workload": w.name, "grid": [w.n, w.n, w.nz], "dof": w.dof, "levels": w.levels,
+                   "a_h": w.a_h, "a_z": w.a_z, "graded": w.graded, "rtol": w.rtol,
+                   "step": "setup + mixed solve + adjoint (lambda solve + dJ/dc)"},
+        "solve": {
+            "mixed_ms": times["mixed"] * 1e3, "fp64_ms": times["fp64"] * 1e3,
+            "speedup_mixed_vs_fp64": times["fp64"] / times["mixed"],
+            "mixed_iterations": im["iterations"], "fp64_iterations": i64["iterations"],
+            "mixed_true_rel_residual": im["true_rel_residual"],
+            "fp64_true_rel_residual": i64["true_rel_residual"],
+            "mixed_vs_fp64_rel_diff": diff,
+            "mixed_dof_iterations_per_s": w.dof * im["iterations"] / times["mixed"],
+            "fp64_dof_iterations_per_s": w.dof * i64["iterations"] / times["fp64"],
+            "forward_iterations": r["info"]["iterations"], "adjoint_iterations": r["info_adj"]["iterations"],
+        },
+        "vcycle_fp32": {"ms": vc_avg_s * 1e3, "model_bytes_per_dof": VCYCLE_WORDS * 4,
+                        "model_GBps": vc_gbs, "frac_hbm_peak": vc_gbs / HBM_PEAK_GBS},
+        "roofline": {"kernel": "k_sweep<float> finest level (general sweep)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "launch_ms": sweep_avg_s * 1e3, "launches": sweep_n,
+                     "algorithmic_bytes_per_launch": sweep_bytes},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a 1/16 sample)")
+        out["cpu_baseline"] = cpu_baseline(w, syn)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * tpmg.h -- C interface of libtpmg: tensor-product geometric multigrid for the
+ * strongly anisotropic pressure (Schur-complement) equation on thin extruded
+ * meshes, after Mitchell & Mueller, "High level implementation of geometric
+ * multigrid solvers for finite element problems: applications in atmospheric
+ * modelling" (arXiv:1605.00492).  Hand-written HIP kernels for gfx950 (MI355X).
+ *
+ * PROBLEM (Sec. 4.2, the approximate Helmholtz operator with diagonally
+ * lumped velocity mass).  Pressure is piecewise constant on a periodic n x n
+ * grid of vertical columns, nz cells per column.  With s_k = dz_k / mean(dz)
+ * and t_{k+1/2} = (s_k + s_{k+1})/2, multigrid level l (n_l = n / 2^l columns
+ * per side, nz unchanged: horizontal semi-coarsening, Sec. 4.2.1) applies
+ *     (H_l x)_p = mu_{l,k} x_p + sum over faces f of p:  w_f (x_p - x_q(f))
+ *     mu_{l,k} = 4^l s_k
+ *     east/north faces:  w_f = a_h s_k c_f
+ *     upper faces (k < nz-1):  w_f = 4^l a_z c_f / t_{k+1/2}
+ * No face lies below k = 0 or above k = nz-1 (u.n = 0 top and bottom,
+ * Sec. 4.1).  Level-0 face coefficients c_f > 0 are the input; a coarse face
+ * takes the mean of the fine faces covering it (rediscretisation, Sec. 3.3).
+ *
+ * METHOD.  Preconditioned CG on H_0 (FP64), preconditioned by one V-cycle
+ * (Sec. 3, two-grid cycle applied recursively) whose smoother is the damped
+ * vertical line relaxation u <- u + omega H_z^{-1}(b - H u) (Sec. 4.2),
+ * H_z being the column-block part of H (tridiagonal, solved exactly per
+ * column, Sec. 4.3.1).  Restriction sums the four horizontal children,
+ * prolongation injects (natural embedding, Sec. 3.2).  The V-cycle may run in
+ * FP32 while the outer CG stays FP64.
+ *
+ * LAYOUTS of device arrays:
+ *   TPMG_LAYOUT_LEVEL_MAJOR  (native) cells x[k][j][i], faces c[f][k][j][i]
+ *   TPMG_LAYOUT_COLUMN_MAJOR (Sec. 4.3 ordering) cells x[j][i][k], faces c[j][i][k][f]
+ * with i fastest in level-major, f in {E=0, N=1, U=2}.  The E face of cell
+ * (i,j,k) joins (i+1 mod n, j, k), the N face joins (i, j+1 mod n, k), the U
+ * face joins (i, j, k+1); the U slot of the top cell holds no face (its value
+ * is ignored on input and its gradient is 0).
+ *
+ * OWNERSHIP.  The caller owns every device buffer, including the workspace
+ * (at least tpmg_workspace_bytes bytes, 256-byte aligned).  The library
+ * allocates no device memory.  A hierarchy handle aliases its workspace: free
+ * the workspace only after tpmg_destroy.  Handles are not thread-safe;
+ * different handles are independent.  Buffers passed to one call must not
+ * alias each other unless stated.
+ *
+ * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  All work is queued on it.  apply/vcycle/smooth/restrict/
+ * prolong/coarse/face_gradient are asynchronous; setup and solve synchronise
+ * the stream (setup for validation and the optional host factorisation,
+ * solve for its convergence tests).
+ *
+ * ERRORS.  Every call returns a tpmg_status; nothing throws across the
+ * interface.  Arguments are validated on the host before any launch.
+ * TPMG_ERR_DEVICE carries the HIP error text in tpmg_last_error().
+ */
+#ifndef TPMG_H
+#define TPMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TPMG_OK = 0,
+    TPMG_NOT_CONVERGED = 1,      /* warning: x holds the last iterate, info is filled  */
+    TPMG_ERR_INVALID_ARG = -1,   /* NULL pointer, bad enum, bad parameter value        */
+    TPMG_ERR_SHAPE = -2,         /* n, nz, nlevels inconsistent or out of range        */
+    TPMG_ERR_NOT_SPD = -3,       /* a face coefficient or dz is not positive and finite */
+    TPMG_ERR_WORKSPACE = -4,     /* workspace missing, too small or misaligned         */
+    TPMG_ERR_DEVICE = -5,        /* a HIP call failed (see tpmg_last_error)            */
+    TPMG_ERR_BREAKDOWN = -6      /* CG breakdown: (p, Hp) <= 0 or non-finite           */
+} tpmg_status;
+
+typedef enum { TPMG_LAYOUT_LEVEL_MAJOR = 0, TPMG_LAYOUT_COLUMN_MAJOR = 1 } tpmg_layout;
+typedef enum { TPMG_FP64 = 0, TPMG_MIXED_FP32_VCYCLE = 1 } tpmg_precision;
+typedef enum { TPMG_COARSE_DIRECT = 0, TPMG_COARSE_SMOOTH = 1 } tpmg_coarse;
+
+/* Problem and multigrid description (all plain values; dz is a host array). */
+typedef struct {
+    int32_t n;          /* columns per side of the periodic grid, n % 2^(nlevels-1) == 0     */
+    int32_t nz;         /* cells per column, 1 <= nz <= TPMG_MAX_NZ                          */
+    int32_t nlevels;    /* multigrid levels, 1 <= nlevels <= TPMG_MAX_LEVELS                 */
+    double a_h, a_z;    /* horizontal / vertical coupling scales (> 0; a_h may be 0)         */
+    const double *dz;   /* host [nz] cell heights > 0, or NULL for uniform                   */
+    int32_t nu_pre;     /* pre-smoothing sweeps per level  (>= 1)                            */
+    int32_t nu_post;    /* post-smoothing sweeps per level (>= 1)                            */
+    double omega;       /* smoother damping, 0 < omega <= 1 (0.8 in Sec. 5)                  */
+    int32_t coarse;     /* tpmg_coarse: exact dense solve or n_coarse sweeps on the coarsest */
+    int32_t n_coarse;   /* sweeps on the coarsest level in SMOOTH mode (>= 1)                */
+    int32_t precision;  /* tpmg_precision of the V-cycle                                     */
+} tpmg_desc;
+
+#define TPMG_MAX_NZ 256
+#define TPMG_MAX_LEVELS 12
+#define TPMG_MAX_DIRECT_DOF 2048   /* largest coarsest level for TPMG_COARSE_DIRECT */
+
+typedef struct {
+    double rtol;         /* stop when ||r||_2 <= rtol ||b||_2 (recursive residual)            */
+    int32_t maxit;       /* iteration limit (>= 0)                                            */
+    int32_t x0_nonzero;  /* 1: x holds the initial guess; 0: start from x = 0                 */
+    int32_t flexible;    /* 1: beta = (r, z - z_old)/(r_old, z_old) (for the FP32 V-cycle)    */
+    double *history;     /* host [maxit+1] for ||r_i||/||b||, or NULL                         */
+} tpmg_solve_opts;
+
+typedef struct {
+    int32_t iterations;        /* applications of H to a search direction               */
+    int32_t converged;         /* 1 if the tolerance was met                            */
+    double rel_residual;       /* last recursive ||r||/||b||                            */
+    double true_rel_residual;  /* ||b - H x||/||b|| recomputed in FP64 at the end       */
+} tpmg_solve_info;
+
+typedef struct tpmg_hierarchy tpmg_hierarchy;
+
+/* Workspace size for a description (validates it: SHAPE / INVALID_ARG / NOT_SPD for dz). */
+tpmg_status tpmg_workspace_bytes(const tpmg_desc *desc, size_t *bytes);
+
+/*
+ * Build the level hierarchy (Sec. 3.1, 3.3): copy c (FP64, 3*n*n*nz values in
+ * `layout`) into the workspace, check every real face coefficient is positive
+ * and finite (TPMG_ERR_NOT_SPD), average faces onto coarse levels, make FP32
+ * copies when precision is mixed, and in DIRECT mode factor and invert the
+ * coarsest operator on the host (at most TPMG_MAX_DIRECT_DOF unknowns).
+ * Synchronises `stream`.  *out receives the handle.  c is not referenced after
+ * the call returns.
+ */
+tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int32_t layout,
+                                 void *workspace_dev, size_t workspace_bytes, void *stream,
+                                 tpmg_hierarchy **out);
+
+/* Columns per side of a level, or -1 for an invalid handle/level. */
+int32_t tpmg_level_n(const tpmg_hierarchy *h, int32_t level);
+
+/*
+ * y = H_level x (Sec. 4.2 operator on that level).  fp32 = 1 uses the FP32
+ * coefficient copies and float buffers (mixed hierarchies only); otherwise
+ * double buffers.  x, y: n_l*n_l*nz values in `layout`; must not alias.
+ */
+tpmg_status tpmg_apply_operator(const tpmg_hierarchy *h, int32_t level, int32_t fp32,
+                                const void *x_dev, void *y_dev, int32_t layout, void *stream);
+
+/*
+ * z = V b: one V-cycle from a zero initial guess on the finest level (the
+ * preconditioner of Sec. 4.2.1).  fp32 as in tpmg_apply_operator.  b, z:
+ * n*n*nz values in `layout`; must not alias.
+ */
+tpmg_status tpmg_vcycle(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev, void *z_dev,
+                        int32_t layout, void *stream);
+
+/*
+ * Solve H_0 x = b by preconditioned CG with one V-cycle per iteration (FP64
+ * outer iteration; FP32 V-cycle on fl32(r) in mixed hierarchies).  b, x: FP64,
+ * n*n*nz values in `layout`.  Returns TPMG_OK, TPMG_NOT_CONVERGED (x holds the
+ * last iterate), TPMG_ERR_BREAKDOWN, or an argument/device error.  info may be
+ * NULL.  Synchronises `stream`.
+ */
+tpmg_status tpmg_solve(const tpmg_hierarchy *h, const double *b_dev, double *x_dev, int32_t layout,
+                       const tpmg_solve_opts *opts, tpmg_solve_info *info, void *stream);
+
+/*
+ * Adjoint face gradient for J(x) with H x = b and lambda = H^{-1} dJ/dx (H is
+ * symmetric, so lambda comes from tpmg_solve on dJ/dx):
+ *     dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q),
+ * gamma_f = a_h s_k (E, N faces), a_z / t_{k+1/2} (U faces); 0 in the U slot
+ * of the top cell.  lambda, x: FP64 cells; grad: FP64 faces (3*n*n*nz),
+ * overwritten; all in `layout`.
+ */
+tpmg_status tpmg_face_gradient(const tpmg_hierarchy *h, const double *lambda_dev,
+                               const double *x_dev, double *grad_dev, int32_t layout, void *stream);
+
+/*
+ * Components of the V-cycle, exposed for testing and composition; level-major
+ * buffers of the hierarchy's precision selected by fp32.
+ *
+ * tpmg_smooth: one damped line-relaxation sweep on a level (Sec. 4.2),
+ *   u_out = u + omega H_z^{-1}(b - H u); u = NULL means u = 0.
+ * tpmg_residual_restrict: b_coarse = R (b - H_level u) on level+1 (Sec. 3.2).
+ * tpmg_prolong_smooth: u_out = S(u + P e), the correction from level+1 added
+ *   by injection followed by one sweep (the first post-smoothing step).
+ * tpmg_coarse_solve: the coarsest-level solve (dense, or n_coarse sweeps from 0).
+ * tpmg_level_coefficients: copy of a level's face coefficients c[f][k][j][i].
+ */
+tpmg_status tpmg_smooth(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *u_dev,
+                        const void *b_dev, void *u_out_dev, void *stream);
+tpmg_status tpmg_residual_restrict(const tpmg_hierarchy *h, int32_t level, int32_t fp32,
+                                   const void *u_dev, const void *b_dev, void *b_coarse_dev,
+                                   void *stream);
+tpmg_status tpmg_prolong_smooth(const tpmg_hierarchy *h, int32_t level, int32_t fp32,
+                                const void *u_dev, const void *e_coarse_dev, const void *b_dev,
+                                void *u_out_dev, void *stream);
+tpmg_status tpmg_coarse_solve(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev,
+                              void *u_dev, void *stream);
+tpmg_status tpmg_level_coefficients(const tpmg_hierarchy *h, int32_t level, int32_t fp32,
+                                    void *c_out_dev, void *stream);
+
+/*
+ * Kernel timing with HIP events recorded on the launch stream around every
+ * launch of one kernel class (for bandwidth accounting).  Enabling resets the
+ * counters.  read synchronises the recorded events and returns the summed
+ * duration and the launch count.
+ */
+typedef enum {
+    TPMG_K_SWEEP = 0,        /* line sweep, general form, finest level          */
+    TPMG_K_SWEEP0 = 1,       /* first pre-sweep from zero, finest level         */
+    TPMG_K_PROLSWEEP = 2,    /* prolongation + sweep, finest level              */
+    TPMG_K_RESTRICT = 3,     /* residual + restriction from the finest level    */
+    TPMG_K_PCG_APPLY = 4,    /* CG direction update + operator apply            */
+    TPMG_K_PCG_UPDATE = 5,   /* CG x / r update                                 */
+    TPMG_K_VCYCLE = 6,       /* one whole V-cycle                               */
+    TPMG_K_COUNT = 7
+} tpmg_kernel_class;
+tpmg_status tpmg_profile_enable(tpmg_hierarchy *h, int32_t enable);
+tpmg_status tpmg_profile_read(tpmg_hierarchy *h, int32_t kernel_class, double *total_ms,
+                              int64_t *launches);
+
+/*
+ * Plain device copy dst <- src of `bytes` bytes (multiple of 16, 16-byte
+ * aligned, non-overlapping) by a streaming kernel: the reference point for
+ * bandwidth and memory-counter calibration.  Asynchronous.
+ */
+tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t bytes, void *stream);
+
+/* Release the handle (not the workspace).  NULL is accepted. */
+tpmg_status tpmg_destroy(tpmg_hierarchy *h);
+
+const char *tpmg_status_string(tpmg_status s);
+/* Last error text of a handle, or of the calling thread when h is NULL. */
+const char *tpmg_last_error(const tpmg_hierarchy *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPMG_H */

@@ -1,0 +1,957 @@
+// Host side of libtpmg: argument validation, workspace layout, hierarchy
+// setup, the V-cycle and CG drivers, and the C interface declared in tpmg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpmg.h"
+#include "tpmg_internal.h"
+
+using namespace tpmg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+
+struct LevelBufs {
+    int n = 0, plane = 0;
+    void *c = nullptr;                       // [3][nz][plane]
+    void *mu = nullptr, *wh = nullptr, *wz = nullptr;  // [nz]
+    void *b = nullptr, *A = nullptr, *B = nullptr, *E = nullptr;  // level vectors
+};
+
+struct EventPool {
+    std::vector<hipEvent_t> start, stop;
+    int used = 0;
+    double acc_ms = 0.0;
+    int64_t launches = 0;
+};
+
+}  // namespace
+
+struct tpmg_hierarchy {
+    tpmg_desc d{};
+    std::vector<double> dz;  // host copy of the spacings (empty = uniform)
+    int L = 0, nz = 0;
+    size_t ncell = 0;        // cells on level 0
+    bool mixed = false;
+    LevelBufs l64[TPMG_MAX_LEVELS], l32[TPMG_MAX_LEVELS];
+    double *ainv64 = nullptr;
+    float *ainv32 = nullptr;
+    int m_coarse = 0;
+    // FP64 vectors for the outer iteration and layout staging
+    double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    double *stage0 = nullptr, *stage1 = nullptr;  // stage0 heads 3 contiguous cell vectors
+    float *r32 = nullptr, *z32 = nullptr;
+    double *partials = nullptr;
+    Scalars *sc = nullptr;
+    int *bad = nullptr;
+    Scalars *sc_host = nullptr;  // pinned
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    bool prof = false;
+    EventPool pools[TPMG_K_COUNT];
+};
+
+namespace {
+
+tpmg_status fail(tpmg_hierarchy *h, tpmg_status s, const std::string &msg)
+{
+    if (h) h->err = msg;
+    g_last_error = msg;
+    return s;
+}
+
+tpmg_status hip_fail(tpmg_hierarchy *h, hipError_t e, const char *where)
+{
+    std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(h, TPMG_ERR_DEVICE, msg);
+}
+
+#define HIP_TRY(h, expr)                                    \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+    } while (0)
+
+tpmg_status validate_desc(const tpmg_desc *d)
+{
+    if (!d) return fail(nullptr, TPMG_ERR_INVALID_ARG, "desc is NULL");
+    if (d->nlevels < 1 || d->nlevels > TPMG_MAX_LEVELS)
+        return fail(nullptr, TPMG_ERR_SHAPE, "nlevels out of range");
+    if (d->nz < 1 || d->nz > TPMG_MAX_NZ) return fail(nullptr, TPMG_ERR_SHAPE, "nz out of range");
+    if (d->n < 1 || d->n > 16384) return fail(nullptr, TPMG_ERR_SHAPE, "n out of range");
+    if (d->n % (1 << (d->nlevels - 1)) != 0)
+        return fail(nullptr, TPMG_ERR_SHAPE, "n must be divisible by 2^(nlevels-1)");
+    const double dof = (double)d->n * d->n * d->nz;
+    // reductions use one partial per workgroup of 256 columns x 16 cells
+    if (dof / (256.0 * 16.0) > (double)kMaxPartials * 0.9 || dof > 2.0e9)
+        return fail(nullptr, TPMG_ERR_SHAPE, "grid too large");
+    if (!(d->a_h >= 0.0) || !(d->a_z >= 0.0) || !std::isfinite(d->a_h) || !std::isfinite(d->a_z))
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "a_h and a_z must be finite and >= 0");
+    if (d->nu_pre < 1 || d->nu_post < 1 || d->nu_pre > 64 || d->nu_post > 64)
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "nu_pre and nu_post must be in [1, 64]");
+    if (!(d->omega > 0.0 && d->omega <= 1.0))
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "omega must be in (0, 1]");
+    if (d->coarse != TPMG_COARSE_DIRECT && d->coarse != TPMG_COARSE_SMOOTH)
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "bad coarse mode");
+    if (d->coarse == TPMG_COARSE_SMOOTH && (d->n_coarse < 1 || d->n_coarse > 64))
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "n_coarse must be in [1, 64]");
+    if (d->precision != TPMG_FP64 && d->precision != TPMG_MIXED_FP32_VCYCLE)
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "bad precision");
+    if (d->coarse == TPMG_COARSE_DIRECT) {
+        const long nc = d->n >> (d->nlevels - 1);
+        if (nc * nc * (long)d->nz > TPMG_MAX_DIRECT_DOF)
+            return fail(nullptr, TPMG_ERR_SHAPE, "coarsest level too large for the direct solve");
+    }
+    int M, P;
+    if (!sweep_shape(d->nz, false, &M, &P)) return fail(nullptr, TPMG_ERR_SHAPE, "nz not supported");
+    if (d->dz)
+        for (int k = 0; k < d->nz; ++k)
+            if (!(d->dz[k] > 0.0) || !std::isfinite(d->dz[k]))
+                return fail(nullptr, TPMG_ERR_NOT_SPD, "dz must be positive and finite");
+    return TPMG_OK;
+}
+
+// Carve the workspace.  With h == nullptr only the size is computed.
+size_t plan_workspace(const tpmg_desc &d, tpmg_hierarchy *h)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        void *p = h ? (void *)(h->ws + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    const bool mixed = d.precision == TPMG_MIXED_FP32_VCYCLE;
+    const size_t nz = (size_t)d.nz;
+    for (int pass = 0; pass < (mixed ? 2 : 1); ++pass) {
+        const size_t S = pass == 0 ? sizeof(double) : sizeof(float);
+        for (int l = 0; l < d.nlevels; ++l) {
+            const int n = d.n >> l;
+            const size_t cells = (size_t)n * n * nz;
+            LevelBufs tmp;
+            LevelBufs &B = h ? (pass == 0 ? h->l64[l] : h->l32[l]) : tmp;
+            B.n = n;
+            B.plane = n * n;
+            B.c = take(3 * cells * S);
+            B.mu = take(nz * S);
+            B.wh = take(nz * S);
+            B.wz = take(nz * S);
+            B.A = take(cells * S);
+            B.B = take(cells * S);
+            if (l > 0) {
+                B.b = take(cells * S);
+                B.E = take(cells * S);
+            }
+        }
+    }
+    const size_t ncell = (size_t)d.n * d.n * nz;
+    if (d.coarse == TPMG_COARSE_DIRECT) {
+        const size_t nc = (size_t)(d.n >> (d.nlevels - 1));
+        const size_t m = nc * nc * nz;
+        void *a64 = take(m * m * sizeof(double));
+        void *a32 = mixed ? take(m * m * sizeof(float)) : nullptr;
+        if (h) {
+            h->ainv64 = (double *)a64;
+            h->ainv32 = (float *)a32;
+            h->m_coarse = (int)m;
+        }
+    }
+    double *vec[5];
+    for (int i = 0; i < 5; ++i) vec[i] = (double *)take(ncell * sizeof(double));
+    double *stage = (double *)take(3 * ncell * sizeof(double));
+    float *r32 = mixed ? (float *)take(ncell * sizeof(float)) : nullptr;
+    float *z32 = mixed ? (float *)take(ncell * sizeof(float)) : nullptr;
+    double *partials = (double *)take(2 * (size_t)kMaxPartials * sizeof(double));
+    Scalars *sc = (Scalars *)take(sizeof(Scalars));
+    int *bad = (int *)take(sizeof(int) * 4);
+    if (h) {
+        h->r = vec[0];
+        h->z = vec[1];
+        h->p0 = vec[2];
+        h->p1 = vec[3];
+        h->q = vec[4];
+        h->stage0 = stage;
+        h->stage1 = stage + ncell;
+        h->r32 = r32;
+        h->z32 = z32;
+        h->partials = partials;
+        h->sc = sc;
+        h->bad = bad;
+    }
+    return (off + kAlign - 1) / kAlign * kAlign;
+}
+
+template <typename T>
+Level<T> level_view(const tpmg_hierarchy *h, int l)
+{
+    const LevelBufs &B = (sizeof(T) == 8) ? h->l64[l] : h->l32[l];
+    Level<T> L;
+    L.n = B.n;
+    L.nz = h->nz;
+    L.plane = B.plane;
+    L.c = (const T *)B.c;
+    L.mu = (const T *)B.mu;
+    L.wh = (const T *)B.wh;
+    L.wz = (const T *)B.wz;
+    return L;
+}
+
+template <typename T>
+const LevelBufs &bufs(const tpmg_hierarchy *h, int l)
+{
+    return (sizeof(T) == 8) ? h->l64[l] : h->l32[l];
+}
+
+// ---- profiling --------------------------------------------------------------
+
+struct Timed {
+    tpmg_hierarchy *h;
+    int cls;
+    hipStream_t s;
+    bool on;
+    Timed(const tpmg_hierarchy *hc, int c, hipStream_t st) : h(const_cast<tpmg_hierarchy *>(hc)), cls(c), s(st)
+    {
+        on = h->prof && cls >= 0;
+        if (!on) return;
+        EventPool &P = h->pools[cls];
+        if (P.used == (int)P.start.size()) {
+            // pool full: fold the recorded pairs into the running total
+            for (int i = 0; i < P.used; ++i) {
+                float ms = 0;
+                (void)hipEventSynchronize(P.stop[i]);
+                (void)hipEventElapsedTime(&ms, P.start[i], P.stop[i]);
+                P.acc_ms += ms;
+            }
+            P.used = 0;
+        }
+        (void)hipEventRecord(P.start[P.used], s);
+    }
+    ~Timed()
+    {
+        if (!on) return;
+        EventPool &P = h->pools[cls];
+        (void)hipEventRecord(P.stop[P.used], s);
+        ++P.used;
+        ++P.launches;
+    }
+};
+
+// ---- V-cycle ----------------------------------------------------------------
+
+template <typename T>
+tpmg_status sweep(const tpmg_hierarchy *h, int l, int mode, const T *u, const T *b, T *out, const T *ec,
+                  hipStream_t s)
+{
+    int cls = -1;
+    if (l == 0) cls = mode == SWEEP_ZERO ? TPMG_K_SWEEP0 : (mode == SWEEP_GENERAL ? TPMG_K_SWEEP : TPMG_K_PROLSWEEP);
+    Timed t(h, cls, s);
+    HIP_TRY(const_cast<tpmg_hierarchy *>(h),
+            launch_sweep<T>(level_view<T>(h, l), mode, u, b, out, ec, (T)h->d.omega, s));
+    return TPMG_OK;
+}
+
+template <typename T>
+tpmg_status coarse_solve(const tpmg_hierarchy *h, const T *b, T *out, hipStream_t s)
+{
+    const int l = h->L - 1;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (h->d.coarse == TPMG_COARSE_DIRECT) {
+        const T *ainv = (sizeof(T) == 8) ? (const T *)h->ainv64 : (const T *)h->ainv32;
+        HIP_TRY(hm, launch_coarse_gemv<T>(ainv, h->m_coarse, b, out, s));
+        return TPMG_OK;
+    }
+    const LevelBufs &B = bufs<T>(h, l);
+    T *A = (T *)B.A, *Bb = (T *)B.B;
+    const int nsw = h->d.n_coarse;
+    const T *prev = nullptr;
+    for (int i = 0; i < nsw; ++i) {
+        T *dst = (i == nsw - 1) ? out : ((i % 2 == 0) ? A : Bb);
+        tpmg_status st = sweep<T>(h, l, i == 0 ? SWEEP_ZERO : SWEEP_GENERAL, prev, b, dst, nullptr, s);
+        if (st != TPMG_OK) return st;
+        prev = dst;
+    }
+    return TPMG_OK;
+}
+
+// z = V_l b (zero initial guess), Sec. 3 cycle M1-M5 applied recursively.
+template <typename T>
+tpmg_status vcycle_level(const tpmg_hierarchy *h, int l, const T *b, T *out, hipStream_t s)
+{
+    if (l == h->L - 1) return coarse_solve<T>(h, b, out, s);
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    const LevelBufs &B = bufs<T>(h, l);
+    const LevelBufs &C = bufs<T>(h, l + 1);
+    T *cur = (T *)B.A, *other = (T *)B.B;
+    tpmg_status st = sweep<T>(h, l, SWEEP_ZERO, nullptr, b, cur, nullptr, s);  // M1
+    if (st != TPMG_OK) return st;
+    for (int i = 1; i < h->d.nu_pre; ++i) {
+        if ((st = sweep<T>(h, l, SWEEP_GENERAL, cur, b, other, nullptr, s)) != TPMG_OK) return st;
+        std::swap(cur, other);
+    }
+    {
+        Timed t(h, l == 0 ? TPMG_K_RESTRICT : -1, s);  // M2
+        HIP_TRY(hm, launch_resid_restrict<T>(level_view<T>(h, l), cur, b, (T *)C.b, s));
+    }
+    if ((st = vcycle_level<T>(h, l + 1, (const T *)C.b, (T *)C.E, s)) != TPMG_OK) return st;  // M3
+    const T *src = cur;
+    for (int i = 0; i < h->d.nu_post; ++i) {  // M4 (fused into the first sweep), M5
+        T *dst = (i == h->d.nu_post - 1) ? out : ((i % 2 == 0) ? other : cur);
+        st = (i == 0) ? sweep<T>(h, l, SWEEP_PROLONG, src, b, dst, (const T *)C.E, s)
+                      : sweep<T>(h, l, SWEEP_GENERAL, src, b, dst, nullptr, s);
+        if (st != TPMG_OK) return st;
+        src = dst;
+    }
+    return TPMG_OK;
+}
+
+template <typename T>
+tpmg_status vcycle(const tpmg_hierarchy *h, const T *b, T *out, hipStream_t s)
+{
+    Timed t(h, TPMG_K_VCYCLE, s);
+    return vcycle_level<T>(h, 0, b, out, s);
+}
+
+// ---- host factorisation of the coarsest operator (direct mode) -----------------
+
+// Dense H on the coarsest level (level-major cell order), assembled from the
+// level's face coefficients and scalars.
+void assemble_dense(const std::vector<double> &c, const std::vector<double> &mu, const std::vector<double> &wh,
+                    const std::vector<double> &wz, int n, int nz, std::vector<double> &A)
+{
+    const int plane = n * n;
+    const size_t m = (size_t)plane * nz;
+    A.assign(m * m, 0.0);
+    const size_t fs = (size_t)plane * nz;
+    auto idx = [&](int i, int j, int k) -> size_t {
+        i = (i % n + n) % n;
+        j = (j % n + n) % n;
+        return (size_t)k * plane + (size_t)j * n + i;
+    };
+    auto couple = [&](size_t p, size_t q, double w) {
+        A[p * m + p] += w;
+        A[q * m + q] += w;
+        A[p * m + q] -= w;
+        A[q * m + p] -= w;
+    };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const size_t p = idx(i, j, k);
+                A[p * m + p] += mu[k];
+                couple(p, idx(i + 1, j, k), wh[k] * c[p]);
+                couple(p, idx(i, j + 1, k), wh[k] * c[fs + p]);
+                if (k + 1 < nz) couple(p, idx(i, j, k + 1), wz[k] * c[2 * fs + p]);
+            }
+}
+
+// A^{-1} of a dense SPD matrix via Cholesky A = C C^T, W = C^{-1}, A^{-1} = W^T W.
+bool spd_inverse(std::vector<double> &A, size_t m, std::vector<double> &Ainv)
+{
+    for (size_t j = 0; j < m; ++j) {
+        double *Aj = &A[j * m];
+        double d = Aj[j];
+        for (size_t p = 0; p < j; ++p) d -= Aj[p] * Aj[p];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        Aj[j] = d;
+        for (size_t i = j + 1; i < m; ++i) {
+            double *Ai = &A[i * m];
+            double s = Ai[j];
+            for (size_t p = 0; p < j; ++p) s -= Ai[p] * Aj[p];
+            Ai[j] = s / d;
+        }
+    }
+    // rows of W = C^{-1}: W[c][i] for i >= c holds (C^{-1})_{i c}
+    std::vector<double> W(m * m, 0.0);
+    for (size_t c = 0; c < m; ++c) {
+        double *w = &W[c * m];
+        for (size_t i = c; i < m; ++i) {
+            const double *Ci = &A[i * m];
+            double s = (i == c) ? 1.0 : 0.0;
+            for (size_t p = c; p < i; ++p) s -= Ci[p] * w[p];
+            w[i] = s / Ci[i];
+        }
+    }
+    Ainv.assign(m * m, 0.0);
+    for (size_t a = 0; a < m; ++a)
+        for (size_t b = a; b < m; ++b) {
+            const double *wa = &W[a * m], *wb = &W[b * m];
+            double s = 0.0;
+            for (size_t i = std::max(a, b); i < m; ++i) s += wa[i] * wb[i];
+            Ainv[a * m + b] = s;
+            Ainv[b * m + a] = s;
+        }
+    return true;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+tpmg_status check_handle(const tpmg_hierarchy *h)
+{
+    if (!h) return fail(nullptr, TPMG_ERR_INVALID_ARG, "hierarchy is NULL");
+    return TPMG_OK;
+}
+
+tpmg_status check_fp32(const tpmg_hierarchy *h, int fp32)
+{
+    if (fp32 != 0 && fp32 != 1) return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "fp32 must be 0 or 1");
+    if (fp32 && !h->mixed)
+        return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG,
+                    "fp32 requires a TPMG_MIXED_FP32_VCYCLE hierarchy");
+    return TPMG_OK;
+}
+
+tpmg_status check_layout(const tpmg_hierarchy *h, int layout)
+{
+    if (layout != TPMG_LAYOUT_LEVEL_MAJOR && layout != TPMG_LAYOUT_COLUMN_MAJOR)
+        return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "bad layout");
+    return TPMG_OK;
+}
+
+tpmg_status check_ptrs(const tpmg_hierarchy *h, std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps) {
+        if (!p) return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "NULL buffer");
+        if (!aligned16(p)) return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "buffer not 16-byte aligned");
+    }
+    return TPMG_OK;
+}
+
+// Reduce the partials of the last launch into the scalars.
+tpmg_status finalize(tpmg_hierarchy *h, int G, int nvals, int stage, int flexible, hipStream_t s)
+{
+    HIP_TRY(h, launch_finalize(h->partials, G, nvals, h->sc, stage, flexible, s));
+    return TPMG_OK;
+}
+
+tpmg_status read_scalars(tpmg_hierarchy *h, hipStream_t s)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->sc_host, h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    return TPMG_OK;
+}
+
+// z = V r in the hierarchy's precision (mixed: r32 must already hold fl32(r)).
+tpmg_status precondition(tpmg_hierarchy *h, hipStream_t s)
+{
+    if (h->mixed) return vcycle<float>(h, h->r32, h->z32, s);
+    return vcycle<double>(h, h->r, h->z, s);
+}
+
+template <typename T>
+tpmg_status smooth_impl(const tpmg_hierarchy *h, int level, const void *u, const void *b, void *out,
+                               hipStream_t s)
+{
+    return sweep<T>(h, level, u ? SWEEP_GENERAL : SWEEP_ZERO, (const T *)u, (const T *)b, (T *)out, nullptr, s);
+}
+
+}  // namespace
+
+// =============================================================================
+// C interface
+// =============================================================================
+
+extern "C" {
+
+tpmg_status tpmg_workspace_bytes(const tpmg_desc *desc, size_t *bytes)
+{
+    tpmg_status st = validate_desc(desc);
+    if (st != TPMG_OK) return st;
+    if (!bytes) return fail(nullptr, TPMG_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = plan_workspace(*desc, nullptr);
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int32_t layout, void *workspace_dev,
+                                 size_t workspace_bytes, void *stream, tpmg_hierarchy **out)
+{
+    tpmg_status st = validate_desc(desc);
+    if (st != TPMG_OK) return st;
+    if (!out) return fail(nullptr, TPMG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (layout != TPMG_LAYOUT_LEVEL_MAJOR && layout != TPMG_LAYOUT_COLUMN_MAJOR)
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "bad layout");
+    if (!c_dev || !aligned16(c_dev)) return fail(nullptr, TPMG_ERR_INVALID_ARG, "c is NULL or misaligned");
+    const size_t need = plan_workspace(*desc, nullptr);
+    if (!workspace_dev || workspace_bytes < need || ((uintptr_t)workspace_dev % kAlign) != 0)
+        return fail(nullptr, TPMG_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+
+    tpmg_hierarchy *h = new tpmg_hierarchy();
+    h->d = *desc;
+    if (desc->dz) h->dz.assign(desc->dz, desc->dz + desc->nz);
+    h->d.dz = nullptr;
+    h->L = desc->nlevels;
+    h->nz = desc->nz;
+    h->ncell = (size_t)desc->n * desc->n * desc->nz;
+    h->mixed = desc->precision == TPMG_MIXED_FP32_VCYCLE;
+    h->ws = (char *)workspace_dev;
+    h->ws_bytes = workspace_bytes;
+    plan_workspace(*desc, h);
+    hipStream_t s = as_stream(stream);
+
+    auto bail = [&](tpmg_status code) {
+        g_last_error = h->err;
+        if (h->sc_host) (void)hipHostFree(h->sc_host);
+        delete h;
+        return code;
+    };
+    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
+
+    // per-level scalars: s_k, t_{k+1/2}
+    const int nz = desc->nz;
+    std::vector<double> sk(nz, 1.0), tk(nz, 1.0);
+    {
+        double mean = 0.0;
+        for (int k = 0; k < nz; ++k) mean += desc->dz ? desc->dz[k] : 1.0;
+        mean /= nz;
+        for (int k = 0; k < nz; ++k) sk[k] = (desc->dz ? desc->dz[k] : 1.0) / mean;
+        for (int k = 0; k + 1 < nz; ++k) tk[k] = 0.5 * (sk[k] + sk[k + 1]);
+    }
+    std::vector<std::vector<double>> mu(h->L), wh(h->L), wz(h->L);
+    for (int l = 0; l < h->L; ++l) {
+        const double f = std::ldexp(1.0, 2 * l);
+        mu[l].resize(nz);
+        wh[l].resize(nz);
+        wz[l].resize(nz);
+        for (int k = 0; k < nz; ++k) {
+            mu[l][k] = f * sk[k];
+            wh[l][k] = desc->a_h * sk[k];
+            wz[l][k] = (k + 1 < nz) ? f * desc->a_z / tk[k] : 0.0;
+        }
+        hipError_t e;
+        if ((e = hipMemcpyAsync(h->l64[l].mu, mu[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(h->l64[l].wh, wh[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(h->l64[l].wz, wz[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return bail(hip_fail(h, e, "copy level scalars"));
+        if (h->mixed) {
+            std::vector<float> m32(nz), h32(nz), z32(nz);
+            for (int k = 0; k < nz; ++k) {
+                m32[k] = (float)mu[l][k];
+                h32[k] = (float)wh[l][k];
+                z32[k] = (float)wz[l][k];
+            }
+            if ((e = hipMemcpyAsync(h->l32[l].mu, m32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(h->l32[l].wh, h32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(h->l32[l].wz, z32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return bail(hip_fail(h, e, "copy level scalars (fp32)"));
+        }
+    }
+    hipError_t e;
+    const int plane0 = desc->n * desc->n;
+    if ((e = launch_copy_coeffs(c_dev, layout, (double *)h->l64[0].c, plane0, nz, s)) != hipSuccess)
+        return bail(hip_fail(h, e, "copy coefficients"));
+    if ((e = launch_fill((double *)h->bad, 0.0, 1, s)) != hipSuccess ||
+        (e = launch_check_coeffs((const double *)h->l64[0].c, plane0, nz, h->bad, s)) != hipSuccess)
+        return bail(hip_fail(h, e, "check coefficients"));
+    for (int l = 0; l + 1 < h->L; ++l)
+        if ((e = launch_coarsen(level_view<double>(h, l), (double *)h->l64[l + 1].c, s)) != hipSuccess)
+            return bail(hip_fail(h, e, "coarsen"));
+    if (h->mixed)
+        for (int l = 0; l < h->L; ++l)
+            if ((e = launch_cast((const double *)h->l64[l].c, (float *)h->l32[l].c,
+                                 3 * (size_t)h->l64[l].plane * nz, s)) != hipSuccess)
+                return bail(hip_fail(h, e, "cast coefficients"));
+    int bad = 0;
+    if ((e = hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(hip_fail(h, e, "setup"));
+    if (bad) return bail(fail(h, TPMG_ERR_NOT_SPD, std::to_string(bad) + " face coefficient(s) not positive and finite"));
+
+    if (desc->coarse == TPMG_COARSE_DIRECT) {
+        const int l = h->L - 1;
+        const int n = h->l64[l].n;
+        const size_t cells = (size_t)n * n * nz;
+        std::vector<double> c(3 * cells);
+        if ((e = hipMemcpy(c.data(), h->l64[l].c, 3 * cells * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+            return bail(hip_fail(h, e, "read coarsest coefficients"));
+        std::vector<double> A, Ainv;
+        assemble_dense(c, mu[l], wh[l], wz[l], n, nz, A);
+        if (!spd_inverse(A, cells, Ainv)) return bail(fail(h, TPMG_ERR_NOT_SPD, "coarsest operator not SPD"));
+        if ((e = hipMemcpy(h->ainv64, Ainv.data(), cells * cells * 8, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(hip_fail(h, e, "upload coarse inverse"));
+        if (h->mixed) {
+            if ((e = launch_cast(h->ainv64, h->ainv32, cells * cells, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return bail(hip_fail(h, e, "cast coarse inverse"));
+        }
+    }
+    *out = h;
+    return TPMG_OK;
+}
+
+int32_t tpmg_level_n(const tpmg_hierarchy *h, int32_t level)
+{
+    if (!h || level < 0 || level >= h->L) return -1;
+    return h->l64[level].n;
+}
+
+tpmg_status tpmg_apply_operator(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *x_dev,
+                                void *y_dev, int32_t layout, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_layout(h, layout)) != TPMG_OK ||
+        (st = check_ptrs(h, {x_dev, y_dev})) != TPMG_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    const int elem = fp32 ? 4 : 8;
+    const int plane = h->l64[level].plane;
+    const void *x = x_dev;
+    void *y = y_dev;
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
+        HIP_TRY(hm, launch_cells_to_level(x_dev, h->stage0, plane, h->nz, elem, s));
+        x = h->stage0;
+        y = h->stage1;
+    }
+    if (fp32)
+        HIP_TRY(hm, launch_apply<float>(level_view<float>(h, level), (const float *)x, (float *)y, s));
+    else
+        HIP_TRY(hm, launch_apply<double>(level_view<double>(h, level), (const double *)x, (double *)y, s));
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(hm, launch_cells_to_column(y, y_dev, plane, h->nz, elem, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_vcycle(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev, void *z_dev, int32_t layout,
+                        void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_layout(h, layout)) != TPMG_OK ||
+        (st = check_ptrs(h, {b_dev, z_dev})) != TPMG_OK)
+        return st;
+    if (b_dev == z_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "b and z must not alias");
+    hipStream_t s = as_stream(stream);
+    const int elem = fp32 ? 4 : 8;
+    const int plane = h->l64[0].plane;
+    const void *b = b_dev;
+    void *z = z_dev;
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
+        HIP_TRY(hm, launch_cells_to_level(b_dev, h->stage0, plane, h->nz, elem, s));
+        b = h->stage0;
+        z = h->stage1;
+    }
+    st = fp32 ? vcycle<float>(h, (const float *)b, (float *)z, s) : vcycle<double>(h, (const double *)b, (double *)z, s);
+    if (st != TPMG_OK) return st;
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(hm, launch_cells_to_column(z, z_dev, plane, h->nz, elem, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_dev, int32_t layout,
+                       const tpmg_solve_opts *opts, tpmg_solve_info *info, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(hc)) != TPMG_OK) return st;
+    tpmg_hierarchy *h = const_cast<tpmg_hierarchy *>(hc);
+    if ((st = check_layout(h, layout)) != TPMG_OK || (st = check_ptrs(h, {b_dev, x_dev})) != TPMG_OK) return st;
+    if (!opts) return fail(h, TPMG_ERR_INVALID_ARG, "opts is NULL");
+    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->flexible != 0 && opts->flexible != 1) ||
+        (opts->x0_nonzero != 0 && opts->x0_nonzero != 1))
+        return fail(h, TPMG_ERR_INVALID_ARG, "bad solve options");
+    if ((const void *)b_dev == (const void *)x_dev) return fail(h, TPMG_ERR_INVALID_ARG, "b and x must not alias");
+    hipStream_t s = as_stream(stream);
+    const size_t n = h->ncell;
+    const int plane = h->l64[0].plane;
+    const Level<double> L0 = level_view<double>(h, 0);
+    const int flex = opts->flexible;
+
+    const double *b = b_dev;
+    double *x = x_dev;
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
+        HIP_TRY(h, launch_cells_to_level(b_dev, h->stage0, plane, h->nz, 8, s));
+        b = h->stage0;
+        x = h->stage1;
+        if (opts->x0_nonzero) HIP_TRY(h, launch_cells_to_level(x_dev, x, plane, h->nz, 8, s));
+    }
+    HIP_TRY(h, launch_fill((double *)h->sc, 0.0, sizeof(Scalars) / sizeof(double), s));
+    int G = 0;
+    if (opts->x0_nonzero) {
+        HIP_TRY(h, launch_residual(L0, x, b, h->r, h->partials, &G, s));
+    } else {
+        HIP_TRY(h, launch_fill(x, 0.0, n, s));
+        HIP_TRY(h, launch_copy(h->r, b, n, s));
+        HIP_TRY(h, launch_dot(n, h->r, h->r, nullptr, h->partials, &G, s));
+    }
+    if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
+    HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+    if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
+    if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+    const double bnorm = std::sqrt(h->sc_host->bb);
+    double rnorm = std::sqrt(h->sc_host->rr);
+    double rel = bnorm > 0 ? rnorm / bnorm : 0.0;
+    if (opts->history) opts->history[0] = rel;
+    int it = 0;
+    bool converged = false;
+    tpmg_status result = TPMG_NOT_CONVERGED;
+    if (!std::isfinite(bnorm) || !std::isfinite(rnorm)) {
+        result = TPMG_ERR_BREAKDOWN;
+        fail(h, result, "non-finite right-hand side or initial residual");
+    } else if (bnorm == 0.0 || rnorm <= opts->rtol * bnorm) {
+        if (bnorm == 0.0) HIP_TRY(h, launch_fill(x, 0.0, n, s));
+        converged = true;
+        result = TPMG_OK;
+    } else {
+        if (h->mixed) HIP_TRY(h, launch_cast(h->r, h->r32, n, s));
+        if ((st = precondition(h, s)) != TPMG_OK) return st;
+        HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_RZ_FIRST, flex, s)) != TPMG_OK) return st;
+        double *pold = h->p1, *pnew = h->p0;
+        for (it = 1; it <= opts->maxit; ++it) {
+            {
+                Timed t(h, TPMG_K_PCG_APPLY, s);
+                HIP_TRY(h, launch_pcg_apply(L0, h->z, h->mixed ? h->z32 : nullptr, pold, pnew, h->q, h->sc,
+                                            it == 1, h->partials, &G, s));
+            }
+            if ((st = finalize(h, G, 1, ST_PQ, flex, s)) != TPMG_OK) return st;
+            {
+                Timed t(h, TPMG_K_PCG_UPDATE, s);
+                HIP_TRY(h, launch_pcg_update(n, x, pnew, h->r, h->q, h->mixed ? h->r32 : nullptr,
+                                             (flex && !h->mixed) ? h->z : nullptr,
+                                             (flex && h->mixed) ? h->z32 : nullptr, h->sc, h->partials, &G, s));
+            }
+            if ((st = finalize(h, G, 2, ST_RR_RZO, flex, s)) != TPMG_OK) return st;
+            if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+            if (h->sc_host->breakdown) {
+                result = TPMG_ERR_BREAKDOWN;
+                fail(h, result, "CG breakdown: (p, Hp) not positive or non-finite scalars");
+                break;
+            }
+            rnorm = std::sqrt(h->sc_host->rr);
+            rel = rnorm / bnorm;
+            if (opts->history) opts->history[it] = rel;
+            if (!std::isfinite(rnorm)) {
+                result = TPMG_ERR_BREAKDOWN;
+                fail(h, result, "non-finite residual");
+                break;
+            }
+            if (rnorm <= opts->rtol * bnorm) {
+                converged = true;
+                result = TPMG_OK;
+                break;
+            }
+            if (it == opts->maxit) break;
+            if ((st = precondition(h, s)) != TPMG_OK) return st;
+            HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s));
+            if ((st = finalize(h, G, 1, ST_RZ, flex, s)) != TPMG_OK) return st;
+            std::swap(pold, pnew);
+        }
+        if (it > opts->maxit) it = opts->maxit;
+    }
+    if (info) {
+        HIP_TRY(h, launch_residual(L0, x, b, h->q, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_TT, 0, s)) != TPMG_OK) return st;
+        if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+        info->iterations = it;
+        info->converged = converged ? 1 : 0;
+        info->rel_residual = rel;
+        info->true_rel_residual = bnorm > 0 ? std::sqrt(h->sc_host->tt) / bnorm : 0.0;
+    }
+    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(h, launch_cells_to_column(x, x_dev, plane, h->nz, 8, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    return result;
+}
+
+tpmg_status tpmg_face_gradient(const tpmg_hierarchy *h, const double *lambda_dev, const double *x_dev,
+                               double *grad_dev, int32_t layout, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if ((st = check_layout(h, layout)) != TPMG_OK || (st = check_ptrs(h, {lambda_dev, x_dev, grad_dev})) != TPMG_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    const int plane = h->l64[0].plane;
+    const Level<double> L0 = level_view<double>(h, 0);
+    if (layout == TPMG_LAYOUT_LEVEL_MAJOR) {
+        HIP_TRY(hm, launch_face_gradient(L0, lambda_dev, x_dev, grad_dev, s));
+        return TPMG_OK;
+    }
+    // column-major: lambda and x staged level-major in r and z (free outside
+    // tpmg_solve), the gradient written level-major to the staging block and
+    // transposed into grad.
+    HIP_TRY(hm, launch_cells_to_level(lambda_dev, h->r, plane, h->nz, 8, s));
+    HIP_TRY(hm, launch_cells_to_level(x_dev, h->z, plane, h->nz, 8, s));
+    HIP_TRY(hm, launch_face_gradient(L0, h->r, h->z, h->stage0, s));
+    HIP_TRY(hm, launch_faces_to_column(h->stage0, grad_dev, plane, h->nz, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_smooth(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *u_dev, const void *b_dev,
+                        void *u_out_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {b_dev, u_out_dev})) != TPMG_OK) return st;
+    if (u_dev && (st = check_ptrs(h, {u_dev})) != TPMG_OK) return st;
+    if (u_dev == u_out_dev || b_dev == u_out_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "output must not alias inputs");
+    hipStream_t s = as_stream(stream);
+    return fp32 ? smooth_impl<float>(h, level, u_dev, b_dev, u_out_dev, s)
+                : smooth_impl<double>(h, level, u_dev, b_dev, u_out_dev, s);
+}
+
+tpmg_status tpmg_residual_restrict(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *u_dev,
+                                   const void *b_dev, void *b_coarse_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level + 1 >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {u_dev, b_dev, b_coarse_dev})) != TPMG_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    if (fp32)
+        HIP_TRY(hm, launch_resid_restrict<float>(level_view<float>(h, level), (const float *)u_dev,
+                                                 (const float *)b_dev, (float *)b_coarse_dev, s));
+    else
+        HIP_TRY(hm, launch_resid_restrict<double>(level_view<double>(h, level), (const double *)u_dev,
+                                                  (const double *)b_dev, (double *)b_coarse_dev, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_prolong_smooth(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *u_dev,
+                                const void *e_coarse_dev, const void *b_dev, void *u_out_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level + 1 >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK ||
+        (st = check_ptrs(h, {u_dev, e_coarse_dev, b_dev, u_out_dev})) != TPMG_OK)
+        return st;
+    if (u_dev == u_out_dev || b_dev == u_out_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "output must not alias inputs");
+    hipStream_t s = as_stream(stream);
+    if (fp32)
+        return sweep<float>(h, level, SWEEP_PROLONG, (const float *)u_dev, (const float *)b_dev, (float *)u_out_dev,
+                            (const float *)e_coarse_dev, s);
+    return sweep<double>(h, level, SWEEP_PROLONG, (const double *)u_dev, (const double *)b_dev, (double *)u_out_dev,
+                         (const double *)e_coarse_dev, s);
+}
+
+tpmg_status tpmg_coarse_solve(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev, void *u_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {b_dev, u_dev})) != TPMG_OK) return st;
+    if (b_dev == u_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "b and u must not alias");
+    hipStream_t s = as_stream(stream);
+    return fp32 ? coarse_solve<float>(h, (const float *)b_dev, (float *)u_dev, s)
+                : coarse_solve<double>(h, (const double *)b_dev, (double *)u_dev, s);
+}
+
+tpmg_status tpmg_level_coefficients(const tpmg_hierarchy *h, int32_t level, int32_t fp32, void *c_out_dev,
+                                    void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {c_out_dev})) != TPMG_OK) return st;
+    const LevelBufs &B = fp32 ? h->l32[level] : h->l64[level];
+    const size_t bytes = 3 * (size_t)B.plane * h->nz * (fp32 ? 4 : 8);
+    HIP_TRY(hm, hipMemcpyAsync(c_out_dev, B.c, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_profile_enable(tpmg_hierarchy *h, int32_t enable)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    for (int c = 0; c < TPMG_K_COUNT; ++c) {
+        EventPool &P = h->pools[c];
+        if (enable && P.start.empty()) {
+            P.start.resize(512);
+            P.stop.resize(512);
+            for (int i = 0; i < 512; ++i) {
+                if (hipEventCreate(&P.start[i]) != hipSuccess || hipEventCreate(&P.stop[i]) != hipSuccess)
+                    return fail(h, TPMG_ERR_DEVICE, "hipEventCreate failed");
+            }
+        }
+        P.used = 0;
+        P.acc_ms = 0.0;
+        P.launches = 0;
+    }
+    h->prof = enable != 0;
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_profile_read(tpmg_hierarchy *h, int32_t kernel_class, double *total_ms, int64_t *launches)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    if (kernel_class < 0 || kernel_class >= TPMG_K_COUNT || !total_ms || !launches)
+        return fail(h, TPMG_ERR_INVALID_ARG, "bad profile query");
+    EventPool &P = h->pools[kernel_class];
+    for (int i = 0; i < P.used; ++i) {
+        float ms = 0;
+        HIP_TRY(h, hipEventSynchronize(P.stop[i]));
+        HIP_TRY(h, hipEventElapsedTime(&ms, P.start[i], P.stop[i]));
+        P.acc_ms += ms;
+    }
+    P.used = 0;
+    *total_ms = P.acc_ms;
+    *launches = P.launches;
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t bytes, void *stream)
+{
+    if (!dst_dev || !src_dev || bytes % 16 || !aligned16(dst_dev) || !aligned16(src_dev))
+        return fail(nullptr, TPMG_ERR_INVALID_ARG, "probe needs 16-byte aligned buffers and a multiple of 16 bytes");
+    hipError_t e = launch_probe_copy(dst_dev, src_dev, bytes, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "probe copy");
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_destroy(tpmg_hierarchy *h)
+{
+    if (!h) return TPMG_OK;
+    for (int c = 0; c < TPMG_K_COUNT; ++c) {
+        for (hipEvent_t e : h->pools[c].start) (void)hipEventDestroy(e);
+        for (hipEvent_t e : h->pools[c].stop) (void)hipEventDestroy(e);
+    }
+    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    delete h;
+    return TPMG_OK;
+}
+
+const char *tpmg_status_string(tpmg_status s)
+{
+    switch (s) {
+    case TPMG_OK: return "ok";
+    case TPMG_NOT_CONVERGED: return "not converged";
+    case TPMG_ERR_INVALID_ARG: return "invalid argument";
+    case TPMG_ERR_SHAPE: return "invalid shape";
+    case TPMG_ERR_NOT_SPD: return "operator not SPD (non-positive coefficient or spacing)";
+    case TPMG_ERR_WORKSPACE: return "workspace missing or too small";
+    case TPMG_ERR_DEVICE: return "HIP device error";
+    case TPMG_ERR_BREAKDOWN: return "CG breakdown";
+    default: return "unknown status";
+    }
+}
+
+const char *tpmg_last_error(const tpmg_hierarchy *h)
+{
+    if (h) return h->err.c_str();
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal declarations shared by the kernels (tpmg_kernels.hip) and the host
+// driver (tpmg_host.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tpmg {
+
+// One multigrid level as the kernels see it.  Level-major storage:
+// cell (i, j, k) at k*plane + j*n + i; faces c[f][k][j][i], f in {E, N, U}.
+template <typename T>
+struct Level {
+    int n;          // columns per side
+    int nz;         // cells per column
+    int plane;      // n * n
+    const T *c;     // [3][nz][plane]; U slot of the top cell holds 0
+    const T *mu;    // [nz]  mass 4^l s_k
+    const T *wh;    // [nz]  horizontal factor a_h s_k
+    const T *wz;    // [nz]  vertical factor 4^l a_z / t_{k+1/2}; wz[nz-1] = 0
+};
+
+// Forms of the line-relaxation sweep kernel.
+enum SweepMode : int {
+    SWEEP_ZERO = 0,     // u = 0:        out = omega H_z^{-1} b
+    SWEEP_GENERAL = 1,  //               out = u + omega H_z^{-1} (b - H u)
+    SWEEP_PROLONG = 2,  // u <- u + P e: out = u + omega H_z^{-1} (b - H u)
+};
+
+// Scalars of the CG iteration, kept in device memory so that kernels read
+// alpha / beta without a host round trip.
+struct Scalars {
+    double bb;        // (b, b)
+    double rr;        // (r, r)
+    double rz;        // (r, z) of the current z
+    double rzo;       // (r_new, z_old) for the flexible beta
+    double pq;        // (p, H p)
+    double alpha;
+    double beta;
+    double tt;        // (b - H x, b - H x) of the final iterate
+    int32_t breakdown;
+    int32_t pad;
+};
+
+enum FinalizeStage : int {
+    ST_BB = 0,
+    ST_RR = 1,
+    ST_RR_RZO = 2,
+    ST_RZ_FIRST = 3,
+    ST_RZ = 4,
+    ST_PQ = 5,
+    ST_TT = 6,
+};
+
+// Upper bound on per-dot partial sums (one per workgroup) in any reduction.
+constexpr int kMaxPartials = 1 << 17;
+
+// ---- launchers (kernels.hip) --------------------------------------------
+// Each returns the launch status.  Shapes are validated by the caller.
+template <typename T>
+hipError_t launch_sweep(const Level<T> &L, int mode, const T *u, const T *b, T *out,
+                        const T *ec, T omega, hipStream_t s);
+template <typename T>
+hipError_t launch_apply(const Level<T> &L, const T *x, T *y, hipStream_t s);
+template <typename T>
+hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *bc, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_gemv(const T *ainv, int m, const T *b, T *x, hipStream_t s);
+
+hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, hipStream_t s);
+hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s);
+hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, int plane, int nz,
+                              hipStream_t s);
+hipError_t launch_check_coeffs(const double *c, int plane, int nz, int *bad, hipStream_t s);
+hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s);
+hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
+// level-major <-> column-major cell transposes (elem = 4 or 8 bytes)
+hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, int elem,
+                                 hipStream_t s);
+hipError_t launch_cells_to_column(const void *src, void *dst, int plane, int nz, int elem,
+                                  hipStream_t s);
+hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int nz,
+                                  hipStream_t s);
+
+// CG building blocks (FP64).  Partial sums go to `partials`; nblocks_out
+// receives the number of partials written per value.
+hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32,
+                            const double *p_old, double *p_new, double *q, const Scalars *sc,
+                            int first, double *partials, int *nblocks_out, hipStream_t s);
+hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q,
+                             float *r32, const double *zold, const float *zold32,
+                             const Scalars *sc, double *partials, int *nblocks_out,
+                             hipStream_t s);
+hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32,
+                      double *partials, int *nblocks_out, hipStream_t s);
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
+                           double *partials, int *nblocks_out, hipStream_t s);
+hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage,
+                           int flexible, hipStream_t s);
+hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x,
+                                double *g, hipStream_t s);
+hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Sweep chunking: cells per lane (M) and waves per column tile (P) for a
+// precision and column height; returns false if nz is not supported.
+bool sweep_shape(int nz, bool fp32, int *M, int *P);
+
+}  // namespace tpmg

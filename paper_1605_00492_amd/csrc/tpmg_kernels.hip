@@ -1,0 +1,998 @@
+// HIP kernels for gfx950 (MI355X): tensor-product multigrid on the lumped
+// pressure operator of Mitchell & Mueller (Sec. 4.2) with vertical line
+// relaxation (Sec. 4.2, 4.3.1), 2x2 horizontal transfers (Sec. 3.2) and the
+// CG building blocks of the outer solve.
+//
+// Every kernel is bandwidth-bound (about 0.5 flop/byte), so the design is
+// about HBM traffic, not the matrix cores:
+//  * level-major storage: a wavefront holds 64 consecutive columns of one
+//    level plane, so every load of a k-plane row is one coalesced segment;
+//  * horizontal neighbours come through the caches from the same or the
+//    adjacent rows, which the XCD-aware block order keeps in one XCD's L2;
+//  * vertical neighbours live in registers (sliding window along k);
+//  * the column solve keeps its whole state in registers: a column is split
+//    into P chunks of M cells, one wavefront per chunk, each chunk eliminated
+//    locally and the P chunks coupled through a small system in LDS.
+#include "tpmg_internal.h"
+
+namespace tpmg {
+
+namespace {
+
+constexpr int kXcds = 8;
+constexpr int kStreamThreads = 256;
+constexpr int kKChunk = 16;  // cells along k per thread in the streaming kernels
+constexpr double kDblMax = 1.7976931348623157e308;
+
+// Workgroups are dispatched to the XCDs round-robin.  Renumber them so that
+// each XCD processes one contiguous range of tiles (neighbouring rows share
+// that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    const int per = G / kXcds, rem = G % kXcds;
+    const int x = b % kXcds, idx = b / kXcds;
+    return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+struct Nbr {
+    int e, w, n, s;
+};
+
+// Periodic horizontal neighbours of column `col` on an n x n plane.
+__device__ __forceinline__ Nbr neighbours(int col, int n, int plane)
+{
+    const int i = col % n, j = col / n;
+    Nbr r;
+    r.e = (i + 1 == n) ? col + 1 - n : col + 1;
+    r.w = (i == 0) ? col + n - 1 : col - 1;
+    r.n = (j + 1 == n) ? col + n - plane : col + n;
+    r.s = (j == 0) ? col + plane - n : col - n;
+    return r;
+}
+
+// Parent column on the next coarser level (natural embedding).
+__device__ __forceinline__ int parent(int col, int n)
+{
+    const int i = col % n, j = col / n;
+    return (j >> 1) * (n >> 1) + (i >> 1);
+}
+
+// Deterministic block reduction of NV values: wavefront shuffle, then the
+// wavefront sums in fixed order; thread 0 writes partials[v * G + bid].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials, int G, int bid)
+{
+    __shared__ double sh[NV][16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < nw; ++q) s += sh[i][q];
+            partials[(size_t)i * G + bid] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Line relaxation sweep.
+//
+//   out = u + omega * H_z^{-1} (b - H u)          (Sec. 4.2, block Jacobi)
+//
+// Workgroup = P wavefronts over the same 64 columns; wavefront p owns cells
+// k in [p*M, p*M + M) of each column.  For its chunk a lane
+//  1. streams k upward, forming the residual r_k, the row excess
+//       e_k = delta_k + w_{k-1/2} e_{k-1} / (w_{k-1/2} + e_{k-1})
+//     (delta_k = mass + horizontal couplings), pivots p_k = e_k + w_{k+1/2}
+//     and the forward eliminations of r and of the unit coupling to the
+//     chunk below (all terms positive: no cancellation in the pivots);
+//  2. back-substitutes to the chunk solution xp with the neighbouring chunks
+//     held at zero, the two spike vectors alpha, beta giving the response to
+//     the cell just below / above the chunk, and gamma = T^{-1} delta, the
+//     response to the row excesses (alpha + beta + gamma = 1 exactly, so
+//     1 - alpha - beta is never formed by subtraction);
+//  3. publishes the chunk-end values to LDS; wavefront 0 solves, per column,
+//     the 2P x 2P system coupling first/last cells of all chunks by a
+//     forward/backward recurrence over chunks whose denominators are sums of
+//     positive terms (accurate in FP32 even when delta << w);
+//  4. forms x = xp + alpha x_below + beta x_above and writes u + omega x.
+// The per-lane state (u, xp, alpha, beta, gamma for M cells) stays in
+// registers.
+// ---------------------------------------------------------------------------
+template <typename T, int M, int MODE>
+__global__ __launch_bounds__(1024) void k_sweep(Level<T> L, const T *__restrict__ u,
+                                                const T *__restrict__ b, T *__restrict__ out,
+                                                const T *__restrict__ ec, T omega)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *red = reinterpret_cast<T *>(smem_raw);  // [P][8][64]
+
+    const int lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int P = blockDim.x >> 6;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int col = tile * 64 + lane;
+    const int nz = L.nz, plane = L.plane;
+    const bool active = col < plane;
+    const int cc = active ? col : 0;
+    const Nbr nb = neighbours(cc, L.n, plane);
+    const size_t fstride = (size_t)nz * plane;
+    const T *cE = L.c;
+    const T *cN = L.c + fstride;
+    const T *cU = L.c + 2 * fstride;
+
+    // Prolongation: every u value read is u + e(parent) (injection).
+    const int nc = L.n >> 1, planec = nc * nc;
+    int pc = 0, pe = 0, pw = 0, pn = 0, ps = 0;
+    if (MODE == SWEEP_PROLONG) {
+        pc = parent(cc, L.n);
+        pe = parent(nb.e, L.n);
+        pw = parent(nb.w, L.n);
+        pn = parent(nb.n, L.n);
+        ps = parent(nb.s, L.n);
+    }
+    auto U = [&](int k, int q, int pq) -> T {
+        T v = u[(size_t)k * plane + q];
+        if (MODE == SWEEP_PROLONG) v += ec[(size_t)k * planec + pq];
+        return v;
+    };
+
+    const int k0 = p * M;
+    T su[M], sy[M], se[M], sg[M], sd[M];
+    T u_dn = 0, u_c = 0, wD = 0;
+    if (k0 < nz) {
+        if (k0 > 0) {
+            wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + cc];
+            if (MODE != SWEEP_ZERO) u_dn = U(k0 - 1, cc, pc);
+        }
+        if (MODE != SWEEP_ZERO) u_c = U(k0, cc, pc);
+    }
+
+    T e_prev = 1, y_prev = 0, eta_prev = 0, g_prev = 0, c_prev = 0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const int k = k0 + t;
+        if (k < nz) {
+            const size_t o = (size_t)k * plane;
+            T u_up = 0;
+            if (MODE != SWEEP_ZERO && k + 1 < nz) u_up = U(k + 1, cc, pc);
+            const T h = L.wh[k];
+            const T mu = L.mu[k];
+            const T wE = h * cE[o + cc];
+            const T wW = h * cE[o + nb.w];
+            const T wN = h * cN[o + cc];
+            const T wS = h * cN[o + nb.s];
+            const T wU = L.wz[k] * cU[o + cc];
+            const T delta = mu + wE + wW + wN + wS;
+            T r = b[o + cc];
+            if (MODE != SWEEP_ZERO) {
+                const T Hu = mu * u_c + wE * (u_c - U(k, nb.e, pe)) + wW * (u_c - U(k, nb.w, pw)) +
+                             wN * (u_c - U(k, nb.n, pn)) + wS * (u_c - U(k, nb.s, ps)) +
+                             wU * (u_c - u_up) + wD * (u_c - u_dn);
+                r -= Hu;
+            }
+            const T e = (t == 0) ? delta + wD : delta + wD * e_prev / (wD + e_prev);
+            const T ip = T(1) / (e + wU);
+            const T g = wU * ip;
+            const T y = (t == 0) ? r : r + g_prev * y_prev;
+            const T eta = (t == 0) ? wD : g_prev * eta_prev;
+            const T cg = (t == 0) ? delta : delta + g_prev * c_prev;
+            su[t] = u_c;
+            sy[t] = y * ip;
+            se[t] = eta * ip;
+            sg[t] = g;
+            sd[t] = cg * ip;
+            e_prev = e;
+            y_prev = y;
+            eta_prev = eta;
+            g_prev = g;
+            c_prev = cg;
+            u_dn = u_c;
+            u_c = u_up;
+            wD = wU;
+        } else {
+            su[t] = 0;
+            sy[t] = 0;
+            se[t] = 0;
+            sg[t] = 0;
+            sd[t] = 0;
+        }
+    }
+
+    // Back substitution inside the chunk: xp, alpha (unit value below), beta
+    // (unit value above) and gamma (row excesses); only the chunk ends of gamma
+    // are kept.
+    T gam_s = 0, gam_e = 0;
+    {
+        T xn = 0, an = 0, bn = 0, cn = 0;
+#pragma unroll
+        for (int t = M - 1; t >= 0; --t) {
+            const T g = sg[t];
+            const T xp = sy[t] + g * xn;
+            const T al = se[t] + g * an;
+            const T be = (t == M - 1) ? g : g * bn;
+            const T ga = sd[t] + g * cn;
+            if (t == M - 1) gam_e = ga;
+            sy[t] = xp;
+            se[t] = al;
+            sg[t] = be;
+            xn = xp;
+            an = al;
+            bn = be;
+            cn = ga;
+        }
+        gam_s = cn;
+    }
+
+    T *rp = red + (size_t)p * 512;
+    rp[lane] = sy[0];
+    rp[64 + lane] = se[0];
+    rp[128 + lane] = sg[0];
+    rp[192 + lane] = gam_s;
+    rp[256 + lane] = sy[M - 1];
+    rp[320 + lane] = se[M - 1];
+    rp[384 + lane] = sg[M - 1];
+    rp[448 + lane] = gam_e;
+    __syncthreads();
+    if (p == 0) {
+        // Chunk q, first cell F_q and last cell L_q:
+        //   F_q = xs + as L_{q-1} + bs F_{q+1},   L_q = xe + ae L_{q-1} + be F_{q+1}.
+        // Forward over chunks with L_{q-1} = phi + psi F_q gives
+        //   F_q = sig + tau F_{q+1},  L_q = phi' + psi' F_{q+1},
+        // where 1 - as psi = (bs + gs) + as (1 - psi) and 1 - psi is carried
+        // by its own positive recurrence.
+        T phi = 0, psi = 0, psib = 1;
+        for (int q = 0; q < P; ++q) {
+            T *rq = red + (size_t)q * 512;
+            const T xs = rq[lane], as = rq[64 + lane], bs = rq[128 + lane], gs = rq[192 + lane];
+            const T xe = rq[256 + lane], ae = rq[320 + lane], be = rq[384 + lane], ge = rq[448 + lane];
+            const T den = (bs + gs) + as * psib;
+            const T rden = T(1) / den;
+            const T sig = (xs + as * phi) * rden;
+            const T tau = bs * rden;
+            const T phin = xe + ae * (phi + psi * sig);
+            const T psin = be + ae * psi * tau;
+            const T psibn = ge + ae * (psib + psi * gs) * rden;
+            rq[lane] = sig;
+            rq[64 + lane] = tau;
+            rq[128 + lane] = phin;
+            rq[192 + lane] = psin;
+            phi = phin;
+            psi = psin;
+            psib = psibn;
+        }
+        T Fn = 0;
+        for (int q = P - 1; q >= 0; --q) {
+            T *rq = red + (size_t)q * 512;
+            const T F = rq[lane] + rq[64 + lane] * Fn;
+            const T Lq = rq[128 + lane] + rq[192 + lane] * Fn;
+            rq[256 + lane] = Lq;
+            rq[320 + lane] = F;
+            Fn = F;
+        }
+    }
+    __syncthreads();
+    const T xlo = (p > 0) ? red[(size_t)(p - 1) * 512 + 256 + lane] : T(0);
+    const T xhi = (p + 1 < P) ? red[(size_t)(p + 1) * 512 + 320 + lane] : T(0);
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int k = k0 + t;
+            if (k < nz) out[(size_t)k * plane + cc] = su[t] + omega * (sy[t] + se[t] * xlo + sg[t] * xhi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y = H x on one level.  Thread = (column, chunk of kKChunk cells).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void stream_coords(const Level<T> &L, int &col, int &k0, bool &active)
+{
+    const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int kc = blk / ncb, cb = blk % ncb;
+    col = cb * kStreamThreads + threadIdx.x;
+    k0 = kc * kKChunk;
+    active = col < L.plane;
+    if (!active) col = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *__restrict__ x,
+                                                          T *__restrict__ y)
+{
+    int col, k0;
+    bool active;
+    stream_coords(L, col, k0, active);
+    const int nz = L.nz, plane = L.plane;
+    const Nbr nb = neighbours(col, L.n, plane);
+    const size_t fstride = (size_t)nz * plane;
+    const T *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    T xm = 0, wD = 0;
+    if (k0 > 0) {
+        xm = x[(size_t)(k0 - 1) * plane + col];
+        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+    }
+    T xc = x[(size_t)k0 * plane + col];
+#pragma unroll 4
+    for (int t = 0; t < kKChunk; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const T xp = (k + 1 < nz) ? x[o + plane + col] : T(0);
+        const T h = L.wh[k];
+        const T wU = L.wz[k] * cU[o + col];
+        const T acc = L.mu[k] * xc + h * cE[o + col] * (xc - x[o + nb.e]) +
+                      h * cE[o + nb.w] * (xc - x[o + nb.w]) + h * cN[o + col] * (xc - x[o + nb.n]) +
+                      h * cN[o + nb.s] * (xc - x[o + nb.s]) + wU * (xc - xp) + wD * (xc - xm);
+        if (active) y[o + col] = acc;
+        xm = xc;
+        xc = xp;
+        wD = wU;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// b_c = R (b - H u): residual on the fine level summed over the four children
+// of each coarse cell (Sec. 3.2).  Couplings between the four children cancel
+// in the sum, so only the eight outer horizontal faces and the vertical faces
+// enter.  Thread = (coarse column, chunk of kKChunk cells).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, const T *__restrict__ u,
+                                                                   const T *__restrict__ b,
+                                                                   T *__restrict__ bc)
+{
+    const int n = L.n, nz = L.nz, plane = L.plane;
+    const int nc = n >> 1, planec = nc * nc;
+    const int ncb = (planec + kStreamThreads - 1) / kStreamThreads;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int kc = blk / ncb, cb = blk % ncb;
+    int ccol = cb * kStreamThreads + threadIdx.x;
+    const bool active = ccol < planec;
+    if (!active) ccol = 0;
+    const int k0 = kc * kKChunk;
+    const int I = ccol % nc, J = ccol / nc;
+    const int i0 = 2 * I, j0 = 2 * J;
+    const int iw = (i0 == 0) ? n - 1 : i0 - 1;
+    const int ie = (i0 + 2 == n) ? 0 : i0 + 2;
+    const int js = (j0 == 0) ? n - 1 : j0 - 1;
+    const int jn = (j0 + 2 == n) ? 0 : j0 + 2;
+    // the four children a=(i0,j0) b=(i0+1,j0) c=(i0,j0+1) d=(i0+1,j0+1)
+    const int q[4] = {j0 * n + i0, j0 * n + i0 + 1, (j0 + 1) * n + i0, (j0 + 1) * n + i0 + 1};
+    const int qw0 = j0 * n + iw, qw1 = (j0 + 1) * n + iw;      // west of a, c
+    const int qe0 = j0 * n + ie, qe1 = (j0 + 1) * n + ie;      // east of b, d
+    const int qs0 = js * n + i0, qs1 = js * n + i0 + 1;        // south of a, b
+    const int qn0 = jn * n + i0, qn1 = jn * n + i0 + 1;        // north of c, d
+    const size_t fstride = (size_t)nz * plane;
+    const T *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+
+    T um[4], uc[4], wD[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        um[a] = 0;
+        wD[a] = 0;
+        if (k0 > 0) {
+            um[a] = u[(size_t)(k0 - 1) * plane + q[a]];
+            wD[a] = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + q[a]];
+        }
+        uc[a] = u[(size_t)k0 * plane + q[a]];
+    }
+#pragma unroll 2
+    for (int t = 0; t < kKChunk; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const T h = L.wh[k], mu = L.mu[k], wz = L.wz[k];
+        T up[4], wU[4];
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            up[a] = (k + 1 < nz) ? u[o + plane + q[a]] : T(0);
+            wU[a] = wz * cU[o + q[a]];
+            s += b[o + q[a]] - mu * uc[a] - wU[a] * (uc[a] - up[a]) - wD[a] * (uc[a] - um[a]);
+        }
+        s -= h * cE[o + qw0] * (uc[0] - u[o + qw0]);
+        s -= h * cE[o + qw1] * (uc[2] - u[o + qw1]);
+        s -= h * cE[o + q[1]] * (uc[1] - u[o + qe0]);
+        s -= h * cE[o + q[3]] * (uc[3] - u[o + qe1]);
+        s -= h * cN[o + qs0] * (uc[0] - u[o + qs0]);
+        s -= h * cN[o + qs1] * (uc[1] - u[o + qs1]);
+        s -= h * cN[o + q[2]] * (uc[2] - u[o + qn0]);
+        s -= h * cN[o + q[3]] * (uc[3] - u[o + qn1]);
+        if (active) bc[(size_t)k * planec + ccol] = s;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            um[a] = uc[a];
+            uc[a] = up[a];
+            wD[a] = wU[a];
+        }
+    }
+}
+
+// Coarsest level, dense mode: x = A^{-1} b with A^{-1} symmetric (row t read
+// as column t, so a wavefront reads consecutive addresses).
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_gemv(const T *__restrict__ ainv, int m,
+                                                     const T *__restrict__ b, T *__restrict__ x)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= m) return;
+    T acc = 0;
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) acc += ainv[(size_t)j * m + t] * b[j];
+    x[t] = acc;
+}
+
+// ---- setup kernels ---------------------------------------------------------
+
+// Level l+1 faces from level l: mean of the fine faces covering each coarse face.
+__global__ __launch_bounds__(256) void k_coarsen(Level<double> F, double *__restrict__ cc)
+{
+    const int n = F.n, nz = F.nz, nc = n >> 1, planec = nc * nc;
+    const size_t total = (size_t)planec * nz;
+    const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total) return;
+    const int k = (int)(g / planec), ccol = (int)(g % planec);
+    const int I = ccol % nc, J = ccol / nc;
+    const size_t fs = (size_t)nz * F.plane, cs = (size_t)nz * planec;
+    const double *cE = F.c, *cN = F.c + fs, *cU = F.c + 2 * fs;
+    const size_t o = (size_t)k * F.plane;
+    const int a = (2 * J) * n + 2 * I;  // child (2I, 2J)
+    cc[g] = 0.5 * (cE[o + a + 1] + cE[o + a + n + 1]);
+    cc[cs + g] = 0.5 * (cN[o + a + n] + cN[o + a + n + 1]);
+    cc[2 * cs + g] = 0.25 * (cU[o + a] + cU[o + a + 1] + cU[o + a + n] + cU[o + a + n + 1]);
+}
+
+__global__ __launch_bounds__(256) void k_cast(const double *__restrict__ s, float *__restrict__ d,
+                                              size_t n)
+{
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256)
+        d[g] = (float)s[g];
+}
+
+// Input faces (either layout) -> level-major copy with the top U slot zeroed.
+__global__ __launch_bounds__(256) void k_copy_coeffs(const double *__restrict__ src, int layout,
+                                                     double *__restrict__ dst, int plane, int nz)
+{
+    const size_t per = (size_t)plane * nz;
+    const size_t total = 3 * per;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
+        const int f = (int)(g / per);
+        const size_t r = g % per;
+        const int k = (int)(r / plane), col = (int)(r % plane);
+        double v = (layout == 0) ? src[g] : src[((size_t)col * nz + k) * 3 + f];
+        if (f == 2 && k == nz - 1) v = 0.0;
+        dst[g] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_check_coeffs(const double *__restrict__ c, int plane, int nz,
+                                                      int *__restrict__ bad)
+{
+    const size_t per = (size_t)plane * nz;
+    const size_t total = 3 * per;
+    int cnt = 0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
+        const int f = (int)(g / per);
+        const int k = (int)((g % per) / plane);
+        if (f == 2 && k == nz - 1) continue;
+        const double v = c[g];
+        if (!(v > 0.0) || !(v <= kDblMax)) ++cnt;
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ x, double v, size_t n)
+{
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) x[g] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy(double *__restrict__ d, const double *__restrict__ s, size_t n)
+{
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) d[g] = s[g];
+}
+
+// Tiled transpose of an R x C row-major matrix (element type E) through LDS.
+template <typename E>
+__global__ __launch_bounds__(256) void k_transpose(const E *__restrict__ src, E *__restrict__ dst,
+                                                   int R, int C)
+{
+    __shared__ E tile[32][33];
+    const int tiles_c = (C + 31) / 32;
+    const int bx = (int)(blockIdx.x % tiles_c) * 32, by = (int)(blockIdx.x / tiles_c) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int r = by + yy, c = bx + tx;
+        if (r < R && c < C) tile[yy][tx] = src[(size_t)r * C + c];
+    }
+    __syncthreads();
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int c = bx + yy, r = by + tx;
+        if (r < R && c < C) dst[(size_t)c * R + r] = tile[tx][yy];
+    }
+}
+
+// Level-major faces [3][nz][plane] -> column-major [plane][nz][3].
+__global__ __launch_bounds__(256) void k_faces_to_column(const double *__restrict__ src,
+                                                         double *__restrict__ dst, int plane, int nz)
+{
+    const size_t per = (size_t)plane * nz;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < 3 * per; g += (size_t)gridDim.x * 256) {
+        const int f = (int)(g / per);
+        const size_t r = g % per;
+        const int k = (int)(r / plane), col = (int)(r % plane);
+        dst[((size_t)col * nz + k) * 3 + f] = src[g];
+    }
+}
+
+// ---- CG kernels (FP64) -----------------------------------------------------
+
+// p_new = z + beta p_old (p_new = z on the first iteration), q = H p_new, and
+// partial sums of (p_new, q).  Neighbour values of p_new are formed on the fly
+// from z and p_old, so p_old and p_new must be different buffers.
+__global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const double *__restrict__ z,
+                                                              const float *__restrict__ z32,
+                                                              const double *__restrict__ p_old,
+                                                              double *__restrict__ p_new,
+                                                              double *__restrict__ q,
+                                                              const Scalars *__restrict__ sc, int first,
+                                                              double *__restrict__ partials)
+{
+    int col, k0;
+    bool active;
+    stream_coords(L, col, k0, active);
+    const int nz = L.nz, plane = L.plane;
+    const Nbr nb = neighbours(col, L.n, plane);
+    const size_t fstride = (size_t)nz * plane;
+    const double *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    const double beta = first ? 0.0 : sc->beta;
+    auto PV = [&](size_t idx) -> double {
+        const double zz = z32 ? (double)z32[idx] : z[idx];
+        return first ? zz : zz + beta * p_old[idx];
+    };
+    double pm = 0, wD = 0;
+    if (k0 > 0) {
+        pm = PV((size_t)(k0 - 1) * plane + col);
+        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+    }
+    double pc = (k0 < nz) ? PV((size_t)k0 * plane + col) : 0.0;
+    double acc_pq = 0;
+#pragma unroll 2
+    for (int t = 0; t < kKChunk; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const double pp = (k + 1 < nz) ? PV(o + plane + col) : 0.0;
+        const double h = L.wh[k];
+        const double wU = L.wz[k] * cU[o + col];
+        const double qq = L.mu[k] * pc + h * cE[o + col] * (pc - PV(o + nb.e)) +
+                          h * cE[o + nb.w] * (pc - PV(o + nb.w)) + h * cN[o + col] * (pc - PV(o + nb.n)) +
+                          h * cN[o + nb.s] * (pc - PV(o + nb.s)) + wU * (pc - pp) + wD * (pc - pm);
+        if (active) {
+            p_new[o + col] = pc;
+            q[o + col] = qq;
+            acc_pq += pc * qq;
+        }
+        pm = pc;
+        pc = pp;
+        wD = wU;
+    }
+    double v[1] = {acc_pq};
+    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+// r = b - H x, and partial sums of (r, r).
+__global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, const double *__restrict__ x,
+                                                             const double *__restrict__ b,
+                                                             double *__restrict__ r,
+                                                             double *__restrict__ partials)
+{
+    int col, k0;
+    bool active;
+    stream_coords(L, col, k0, active);
+    const int nz = L.nz, plane = L.plane;
+    const Nbr nb = neighbours(col, L.n, plane);
+    const size_t fstride = (size_t)nz * plane;
+    const double *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    double xm = 0, wD = 0;
+    if (k0 > 0) {
+        xm = x[(size_t)(k0 - 1) * plane + col];
+        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+    }
+    double xc = (k0 < nz) ? x[(size_t)k0 * plane + col] : 0.0;
+    double acc = 0;
+    for (int t = 0; t < kKChunk; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const double xp = (k + 1 < nz) ? x[o + plane + col] : 0.0;
+        const double h = L.wh[k];
+        const double wU = L.wz[k] * cU[o + col];
+        const double hx = L.mu[k] * xc + h * cE[o + col] * (xc - x[o + nb.e]) +
+                          h * cE[o + nb.w] * (xc - x[o + nb.w]) + h * cN[o + col] * (xc - x[o + nb.n]) +
+                          h * cN[o + nb.s] * (xc - x[o + nb.s]) + wU * (xc - xp) + wD * (xc - xm);
+        if (active) {
+            const double rr = b[o + col] - hx;
+            r[o + col] = rr;
+            acc += rr * rr;
+        }
+        xm = xc;
+        xc = xp;
+        wD = wU;
+    }
+    double v[1] = {acc};
+    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+// x += alpha p; r -= alpha q; partial (r,r) and, when z_old is given, (r, z_old);
+// optionally r32 = fl32(r) for the FP32 V-cycle.
+__global__ __launch_bounds__(256) void k_pcg_update(size_t n, double *__restrict__ x,
+                                                    const double *__restrict__ p, double *__restrict__ r,
+                                                    const double *__restrict__ q, float *__restrict__ r32,
+                                                    const double *__restrict__ zold,
+                                                    const float *__restrict__ zold32,
+                                                    const Scalars *__restrict__ sc,
+                                                    double *__restrict__ partials)
+{
+    const double alpha = sc->alpha;
+    double rr = 0, rz = 0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        x[g] += alpha * p[g];
+        const double rv = r[g] - alpha * q[g];
+        r[g] = rv;
+        rr += rv * rv;
+        if (r32) r32[g] = (float)rv;
+        if (zold) rz += rv * zold[g];
+        if (zold32) rz += rv * (double)zold32[g];
+    }
+    double v[2] = {rr, rz};
+    block_partials<2>(v, partials, gridDim.x, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_dot(size_t n, const double *__restrict__ a,
+                                             const double *__restrict__ b, const float *__restrict__ b32,
+                                             double *__restrict__ partials)
+{
+    double s = 0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256)
+        s += a[g] * (b32 ? (double)b32[g] : b[g]);
+    double v[1] = {s};
+    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+// Fixed-order sum of the partials and the scalar recurrences of CG.
+__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ partials, int G, int nvals,
+                                                   Scalars *__restrict__ sc, int stage, int flexible)
+{
+    __shared__ double sh[2][1024];
+    for (int v = 0; v < nvals; ++v) {
+        double s = 0;
+        for (int i = threadIdx.x; i < G; i += 1024) s += partials[(size_t)v * G + i];
+        sh[v][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < nvals; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double s0 = sh[0][0], s1 = (nvals > 1) ? sh[1][0] : 0.0;
+    switch (stage) {
+    case ST_BB: sc->bb = s0; break;
+    case ST_RR: sc->rr = s0; break;
+    case ST_RR_RZO: sc->rr = s0; sc->rzo = s1; break;
+    case ST_RZ_FIRST:
+        sc->rz = s0;
+        sc->beta = 0.0;
+        if (!(fabs(s0) <= kDblMax)) sc->breakdown = 1;
+        break;
+    case ST_RZ: {
+        const double num = flexible ? s0 - sc->rzo : s0;
+        sc->beta = num / sc->rz;
+        sc->rz = s0;
+        if (!(fabs(sc->beta) <= kDblMax)) sc->breakdown = 1;
+        break;
+    }
+    case ST_PQ: {
+        sc->pq = s0;
+        const double a = sc->rz / s0;
+        if (!(s0 > 0.0) || !(fabs(a) <= kDblMax)) {
+            sc->breakdown = 1;
+            sc->alpha = 0.0;
+        } else {
+            sc->alpha = a;
+        }
+        break;
+    }
+    case ST_TT: sc->tt = s0; break;
+    default: break;
+    }
+}
+
+// dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q) on level-0 faces.
+__global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> L,
+                                                                  const double *__restrict__ lam,
+                                                                  const double *__restrict__ x,
+                                                                  double *__restrict__ g)
+{
+    int col, k0;
+    bool active;
+    stream_coords(L, col, k0, active);
+    const int nz = L.nz, plane = L.plane;
+    const Nbr nb = neighbours(col, L.n, plane);
+    const size_t fstride = (size_t)nz * plane;
+    double lc = (k0 < nz) ? lam[(size_t)k0 * plane + col] : 0.0;
+    double xc = (k0 < nz) ? x[(size_t)k0 * plane + col] : 0.0;
+    for (int t = 0; t < kKChunk; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const double h = L.wh[k];
+        const double lu = (k + 1 < nz) ? lam[o + plane + col] : 0.0;
+        const double xu = (k + 1 < nz) ? x[o + plane + col] : 0.0;
+        const double gE = -h * (lc - lam[o + nb.e]) * (xc - x[o + nb.e]);
+        const double gN = -h * (lc - lam[o + nb.n]) * (xc - x[o + nb.n]);
+        const double gU = (k + 1 < nz) ? -L.wz[k] * (lc - lu) * (xc - xu) : 0.0;
+        if (active) {
+            g[o + col] = gE;
+            g[fstride + o + col] = gN;
+            g[2 * fstride + o + col] = gU;
+        }
+        lc = lu;
+        xc = xu;
+    }
+}
+
+// Streaming copy with 16-byte accesses: the bandwidth reference point.
+__global__ __launch_bounds__(256) void k_probe_copy(const uint4 *__restrict__ s, uint4 *__restrict__ d,
+                                                    size_t n)
+{
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) d[g] = s[g];
+}
+
+int grid_for(size_t n, int per_thread = 4)
+{
+    size_t g = (n + (size_t)256 * per_thread - 1) / ((size_t)256 * per_thread);
+    if (g < 1) g = 1;
+    if (g > (size_t)kMaxPartials) g = kMaxPartials;
+    return (int)g;
+}
+
+template <typename T>
+int stream_grid(const Level<T> &L)
+{
+    const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
+    const int nkc = (L.nz + kKChunk - 1) / kKChunk;
+    return ncb * nkc;
+}
+
+template <typename T, int M>
+hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega,
+                   int P, hipStream_t s)
+{
+    const int tiles = (L.plane + 63) / 64;
+    const dim3 block(64 * P);
+    const size_t lds = (size_t)P * 512 * sizeof(T);
+    switch (mode) {
+    case SWEEP_ZERO:
+        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_ZERO>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        break;
+    case SWEEP_GENERAL:
+        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_GENERAL>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        break;
+    default:
+        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_PROLONG>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sweep_shape(int nz, bool fp32, int *M, int *P)
+{
+    const int target = fp32 ? 16 : 8;
+    const int cand[3] = {4, 8, 16};
+    const int want = nz < target ? nz : target;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int m : cand) {
+            if (pass == 0 && m < want) continue;
+            const int p = (nz + m - 1) / m;
+            if (p <= 16) {
+                *M = m;
+                *P = p;
+                return true;
+            }
+        }
+    return false;
+}
+
+template <typename T>
+hipError_t launch_sweep(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec,
+                        T omega, hipStream_t s)
+{
+    int M = 0, P = 0;
+    if (!sweep_shape(L.nz, sizeof(T) == 4, &M, &P)) return hipErrorInvalidValue;
+    switch (M) {
+    case 4: return sweep_m<T, 4>(L, mode, u, b, out, ec, omega, P, s);
+    case 8: return sweep_m<T, 8>(L, mode, u, b, out, ec, omega, P, s);
+    default: return sweep_m<T, 16>(L, mode, u, b, out, ec, omega, P, s);
+    }
+}
+
+template <typename T>
+hipError_t launch_apply(const Level<T> &L, const T *x, T *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply<T>, dim3(stream_grid(L)), dim3(kStreamThreads), 0, s, L, x, y);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *bc, hipStream_t s)
+{
+    const int planec = (L.n / 2) * (L.n / 2);
+    const int ncb = (planec + kStreamThreads - 1) / kStreamThreads;
+    const int nkc = (L.nz + kKChunk - 1) / kKChunk;
+    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(ncb * nkc), dim3(kStreamThreads), 0, s, L, u, b, bc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_gemv(const T *ainv, int m, const T *b, T *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coarse_gemv<T>, dim3((m + 255) / 256), dim3(256), 0, s, ainv, m, b, x);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep<double>(const Level<double> &, int, const double *, const double *,
+                                         double *, const double *, double, hipStream_t);
+template hipError_t launch_sweep<float>(const Level<float> &, int, const float *, const float *, float *,
+                                        const float *, float, hipStream_t);
+template hipError_t launch_apply<double>(const Level<double> &, const double *, double *, hipStream_t);
+template hipError_t launch_apply<float>(const Level<float> &, const float *, float *, hipStream_t);
+template hipError_t launch_resid_restrict<double>(const Level<double> &, const double *, const double *,
+                                                  double *, hipStream_t);
+template hipError_t launch_resid_restrict<float>(const Level<float> &, const float *, const float *,
+                                                 float *, hipStream_t);
+template hipError_t launch_coarse_gemv<double>(const double *, int, const double *, double *, hipStream_t);
+template hipError_t launch_coarse_gemv<float>(const float *, int, const float *, float *, hipStream_t);
+
+hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, hipStream_t s)
+{
+    const size_t total = (size_t)(F.n / 2) * (F.n / 2) * F.nz;
+    hipLaunchKernelGGL(k_coarsen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F, c_coarse);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cast, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, int plane, int nz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_coeffs, dim3(grid_for(3 * (size_t)plane * nz)), dim3(256), 0, s, src, layout,
+                       dst, plane, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_coeffs(const double *c, int plane, int nz, int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_coeffs, dim3(grid_for(3 * (size_t)plane * nz)), dim3(256), 0, s, c, plane, nz,
+                       bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+static hipError_t transpose_elem(const void *src, void *dst, int R, int C, int elem, hipStream_t s)
+{
+    const dim3 grid((unsigned)(((C + 31) / 32) * (size_t)((R + 31) / 32)));
+    if (elem == 8)
+        hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, s, (const double *)src, (double *)dst, R, C);
+    else
+        hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, (const float *)src, (float *)dst, R, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, int elem, hipStream_t s)
+{
+    return transpose_elem(src, dst, plane, nz, elem, s);  // [plane][nz] -> [nz][plane]
+}
+
+hipError_t launch_cells_to_column(const void *src, void *dst, int plane, int nz, int elem, hipStream_t s)
+{
+    return transpose_elem(src, dst, nz, plane, elem, s);  // [nz][plane] -> [plane][nz]
+}
+
+hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int nz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_faces_to_column, dim3(grid_for(3 * (size_t)plane * nz)), dim3(256), 0, s, src, dst,
+                       plane, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32, const double *p_old,
+                            double *p_new, double *q, const Scalars *sc, int first, double *partials,
+                            int *nblocks_out, hipStream_t s)
+{
+    const int G = stream_grid(L);
+    *nblocks_out = G;
+    hipLaunchKernelGGL(k_pcg_apply, dim3(G), dim3(kStreamThreads), 0, s, L, z, z32, p_old, p_new, q, sc, first,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
+                           double *partials, int *nblocks_out, hipStream_t s)
+{
+    const int G = stream_grid(L);
+    *nblocks_out = G;
+    hipLaunchKernelGGL(k_residual, dim3(G), dim3(kStreamThreads), 0, s, L, x, b, r, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q, float *r32,
+                             const double *zold, const float *zold32, const Scalars *sc, double *partials,
+                             int *nblocks_out, hipStream_t s)
+{
+    const int G = grid_for(n);
+    *nblocks_out = G;
+    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(256), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32, double *partials,
+                      int *nblocks_out, hipStream_t s)
+{
+    const int G = grid_for(n);
+    *nblocks_out = G;
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(256), 0, s, n, a, b, b32, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage, int flexible,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, nblocks, nvals, sc, stage, flexible);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x, double *g,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_face_gradient, dim3(stream_grid(L)), dim3(kStreamThreads), 0, s, L, lam, x, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(n, 8)), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace tpmg
