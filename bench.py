@@ -79,6 +79,60 @@ def cpu_baseline(w, syn):
                       f"{dt:.1f} s"}
 
 
+def probe(tp, torch, w, c, b, kw, args):
+    """Each finest-level kernel of the V-cycle (both precisions) and a plain
+    1 GiB device copy, timed with HIP events: the workload for rocprofv3
+    counter passes and for kernel tuning.  Algorithmic bytes per DOF are
+    words x word size: sweep0 5, sweep 6, prolongation+sweep 6.25,
+    residual+restriction 5.25, apply 5."""
+    H = tp.Hierarchy(c, precision="mixed", **kw)
+    nc = H.level_n(1)
+    res = {}
+    for dt, S in ((torch.float32, 4), (torch.float64, 8)):
+        tag = "fp32" if S == 4 else "fp64"
+        bb = b.to(dt)
+        u = torch.empty_like(bb).normal_()
+        e = torch.empty((w.nz, nc, nc), dtype=dt, device=c.device).normal_()
+        kernels = {
+            "sweep0": (lambda: H.smooth(bb), 5.0),
+            "sweep": (lambda: H.smooth(bb, u), 6.0),
+            "prolsweep": (lambda: H.prolong_smooth(u, e, bb), 6.25),
+            "restrict": (lambda: H.residual_restrict(u, bb), 5.25),
+            "apply": (lambda: H.apply(u), 5.0),
+        }
+        for name, (fn, words) in kernels.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            res[f"{tag}_{name}_ms"] = ms
+            res[f"{tag}_{name}_GBps"] = words * S * w.dof / (ms * 1e-3) / 1e9
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=c.device)
+    dst = torch.empty_like(src)
+    tp.bandwidth_probe(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        tp.bandwidth_probe(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    res["copy_ms"] = e0.elapsed_time(e1) / args.steps
+    res["copy_GBps"] = 2 * nbytes / (res["copy_ms"] * 1e-3) / 1e9
+    res["copy_bytes_each_way"] = nbytes
+    res["dof"] = w.dof
+    res["kernel_source_hash"] = kernel_hash()
+    res["env"] = {k: v for k, v in os.environ.items() if k.startswith("TPMG_")}
+    print(json.dumps(res), flush=True)
+    H.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large_1024x1024x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="only run the finest-level FP32 sweep and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -107,6 +163,9 @@ def main():
     kw = dict(dz=w.dz(), a_h=w.a_h, a_z=w.a_z, levels=w.levels, nu=w.nu, omega=w.omega,
               coarse=w.coarse, n_coarse=w.n_coarse)
     torch.cuda.synchronize()
+    if args.probe:
+        probe(tp, torch, w, c, b, kw, args)
+        return
 
     def step(record=None):
         H = tp.Hierarchy(c, precision="mixed", **kw)

@@ -112,8 +112,9 @@ tpmg_status validate_desc(const tpmg_desc *d)
         if (nc * nc * (long)d->nz > TPMG_MAX_DIRECT_DOF)
             return fail(nullptr, TPMG_ERR_SHAPE, "coarsest level too large for the direct solve");
     }
-    int M, P;
-    if (!sweep_shape(d->nz, false, &M, &P)) return fail(nullptr, TPMG_ERR_SHAPE, "nz not supported");
+    int M, CPW, P;
+    if (!sweep_shape(d->nz, false, &M, &CPW, &P) || !sweep_shape(d->nz, true, &M, &CPW, &P))
+        return fail(nullptr, TPMG_ERR_SHAPE, "nz not supported");
     if (d->dz)
         for (int k = 0; k < d->nz; ++k)
             if (!(d->dz[k] > 0.0) || !std::isfinite(d->dz[k]))

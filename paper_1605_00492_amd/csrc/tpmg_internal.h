@@ -103,8 +103,9 @@ hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const
                                 double *g, hipStream_t s);
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-// Sweep chunking: cells per lane (M) and waves per column tile (P) for a
-// precision and column height; returns false if nz is not supported.
-bool sweep_shape(int nz, bool fp32, int *M, int *P);
+// Sweep chunking for a precision and column height: M cells per chunk, CPW
+// chunks per wavefront, P wavefronts per 64-column tile; false if nz is not
+// supported.
+bool sweep_shape(int nz, bool fp32, int *M, int *CPW, int *P);
 
 }  // namespace tpmg

@@ -13,6 +13,8 @@
 //  * the column solve keeps its whole state in registers: a column is split
 //    into P chunks of M cells, one wavefront per chunk, each chunk eliminated
 //    locally and the P chunks coupled through a small system in LDS.
+#include <cstdlib>
+
 #include "tpmg_internal.h"
 
 namespace tpmg {
@@ -32,6 +34,50 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     const int per = G / kXcds, rem = G % kXcds;
     const int x = b % kXcds, idx = b / kXcds;
     return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// 1/x: the hardware reciprocal in FP32 (1 ulp), IEEE division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Element idx of a wave-uniform row pointer, with the byte offset formed in
+// 32 bits so that the load uses a scalar base + 32-bit vector offset (rows
+// hold fewer than 2^29 elements).
+template <typename T>
+__device__ __forceinline__ T ldrow(const T *base, unsigned idx)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(T));
+}
+
+// Raw buffer access: a 128-bit descriptor per array (scalar registers), a
+// per-lane byte offset and a wave-uniform byte offset (the k plane).  Reads
+// beyond the descriptor's size return 0 and writes beyond it are dropped.
+// Arrays addressed this way hold fewer than 2^32 bytes.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, size_t bytes)
+{
+    const unsigned n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, kRsrcWord3);
+}
+
+__device__ __forceinline__ float bload(float, Rsrc r, unsigned voff, unsigned soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bload(double, Rsrc r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          (int)voff, (int)soff, 0);
 }
 
 struct Nbr {
@@ -88,160 +134,212 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
 //
 //   out = u + omega * H_z^{-1} (b - H u)          (Sec. 4.2, block Jacobi)
 //
-// Workgroup = P wavefronts over the same 64 columns; wavefront p owns cells
-// k in [p*M, p*M + M) of each column.  For its chunk a lane
+// A column of nz cells is split into Q chunks of M cells.  A workgroup holds
+// the chunks of 64 columns; each of its P wavefronts advances CPW chunks in
+// lockstep (chunk q = c * P + p), so one step of a wavefront issues the loads
+// of CPW cells at once.  For each chunk a lane
 //  1. streams k upward, forming the residual r_k, the row excess
 //       e_k = delta_k + w_{k-1/2} e_{k-1} / (w_{k-1/2} + e_{k-1})
 //     (delta_k = mass + horizontal couplings), pivots p_k = e_k + w_{k+1/2}
 //     and the forward eliminations of r and of the unit coupling to the
 //     chunk below (all terms positive: no cancellation in the pivots);
 //  2. back-substitutes to the chunk solution xp with the neighbouring chunks
-//     held at zero, the two spike vectors alpha, beta giving the response to
-//     the cell just below / above the chunk, and gamma = T^{-1} delta, the
-//     response to the row excesses (alpha + beta + gamma = 1 exactly, so
-//     1 - alpha - beta is never formed by subtraction);
+//     held at zero, the spike vectors alpha, beta (response to the cell just
+//     below / above the chunk) and, in FP32, gamma = T^{-1} delta (response to
+//     the row excesses; alpha + beta + gamma = 1, so 1 - alpha - beta is never
+//     formed by subtraction in FP32);
 //  3. publishes the chunk-end values to LDS; wavefront 0 solves, per column,
-//     the 2P x 2P system coupling first/last cells of all chunks by a
-//     forward/backward recurrence over chunks whose denominators are sums of
-//     positive terms (accurate in FP32 even when delta << w);
+//     the system coupling first/last cells of all chunks by a forward /
+//     backward recurrence over chunks whose denominators are sums of positive
+//     terms;
 //  4. forms x = xp + alpha x_below + beta x_above and writes u + omega x.
-// The per-lane state (u, xp, alpha, beta, gamma for M cells) stays in
-// registers.
+// The per-lane state (u, xp, alpha, beta[, gamma] for CPW x M cells) stays in
+// registers; loads use buffer descriptors with a per-k scalar offset.
 // ---------------------------------------------------------------------------
-template <typename T, int M, int MODE>
-__global__ __launch_bounds__(1024) void k_sweep(Level<T> L, const T *__restrict__ u,
-                                                const T *__restrict__ b, T *__restrict__ out,
-                                                const T *__restrict__ ec, T omega)
+template <typename T>
+struct SweepRaw {
+    T uup, uE, uW, uN, uS, b, cE, cEw, cN, cNs, cU;
+};
+
+template <typename T, int M, int CPW, int MODE, int LB>
+__global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
+                                              T *__restrict__ out, const T *__restrict__ ec, T omega)
 {
+    constexpr bool kGamma = sizeof(T) == 4;
+    constexpr unsigned S = sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *red = reinterpret_cast<T *>(smem_raw);  // [P][8][64]
+    T *red = reinterpret_cast<T *>(smem_raw);  // [Q][8][64]
 
     const int lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = blockDim.x >> 6;
+    const int Q = P * CPW;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int col = tile * 64 + lane;
     const int nz = L.nz, plane = L.plane;
     const bool active = col < plane;
-    const int cc = active ? col : 0;
+    const unsigned cc = active ? col : 0;
     const Nbr nb = neighbours(cc, L.n, plane);
     const size_t fstride = (size_t)nz * plane;
-    const T *cE = L.c;
-    const T *cN = L.c + fstride;
-    const T *cU = L.c + 2 * fstride;
+    const Rsrc rb = make_rsrc(b, fstride * S);
+    const Rsrc rE = make_rsrc(L.c, fstride * S);
+    const Rsrc rN = make_rsrc(L.c + fstride, fstride * S);
+    const Rsrc rU = make_rsrc(L.c + 2 * fstride, fstride * S);
+    const Rsrc ru = make_rsrc(u, MODE == SWEEP_ZERO ? 0 : fstride * S);
+    const unsigned oc = cc * S, oe = nb.e * S, ow = nb.w * S, on = nb.n * S, os = nb.s * S;
+    const unsigned pstride = (unsigned)plane * S;
 
     // Prolongation: every u value read is u + e(parent) (injection).
     const int nc = L.n >> 1, planec = nc * nc;
-    int pc = 0, pe = 0, pw = 0, pn = 0, ps = 0;
+    const Rsrc re = make_rsrc(ec, MODE == SWEEP_PROLONG ? (size_t)nz * planec * S : 0);
+    const unsigned cstride = (unsigned)planec * S;
+    unsigned pc = 0, pe = 0, pw = 0, pn = 0, ps = 0;
     if (MODE == SWEEP_PROLONG) {
-        pc = parent(cc, L.n);
-        pe = parent(nb.e, L.n);
-        pw = parent(nb.w, L.n);
-        pn = parent(nb.n, L.n);
-        ps = parent(nb.s, L.n);
+        pc = parent(cc, L.n) * S;
+        pe = parent(nb.e, L.n) * S;
+        pw = parent(nb.w, L.n) * S;
+        pn = parent(nb.n, L.n) * S;
+        ps = parent(nb.s, L.n) * S;
     }
-    auto U = [&](int k, int q, int pq) -> T {
-        T v = u[(size_t)k * plane + q];
-        if (MODE == SWEEP_PROLONG) v += ec[(size_t)k * planec + pq];
+    auto U = [&](int k, unsigned o, unsigned po) -> T {
+        T v = bload(T(), ru, o, (unsigned)k * pstride);
+        if (MODE == SWEEP_PROLONG) v += bload(T(), re, po, (unsigned)k * cstride);
         return v;
     };
 
-    const int k0 = p * M;
-    T su[M], sy[M], se[M], sg[M], sd[M];
-    T u_dn = 0, u_c = 0, wD = 0;
-    if (k0 < nz) {
-        if (k0 > 0) {
-            wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + cc];
-            if (MODE != SWEEP_ZERO) u_dn = U(k0 - 1, cc, pc);
+    T su[CPW][M], sy[CPW][M], se[CPW][M], sg[CPW][M], sd[CPW][kGamma ? M : 1];
+    T u_dn[CPW], u_c[CPW], wD[CPW], e_prev[CPW], y_prev[CPW], eta_prev[CPW], g_prev[CPW], c_prev[CPW];
+    int k0[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        k0[c] = (c * P + p) * M;
+        u_dn[c] = u_c[c] = wD[c] = T(0);
+        if (k0[c] < nz) {
+            if (k0[c] > 0) {
+                wD[c] = L.wz[k0[c] - 1] * bload(T(), rU, oc, (unsigned)(k0[c] - 1) * pstride);
+                if (MODE != SWEEP_ZERO) u_dn[c] = U(k0[c] - 1, oc, pc);
+            }
+            if (MODE != SWEEP_ZERO) u_c[c] = U(k0[c], oc, pc);
         }
-        if (MODE != SWEEP_ZERO) u_c = U(k0, cc, pc);
+        e_prev[c] = T(1);
+        y_prev[c] = eta_prev[c] = g_prev[c] = c_prev[c] = T(0);
     }
 
-    T e_prev = 1, y_prev = 0, eta_prev = 0, g_prev = 0, c_prev = 0;
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-        const int k = k0 + t;
-        if (k < nz) {
-            const size_t o = (size_t)k * plane;
-            T u_up = 0;
-            if (MODE != SWEEP_ZERO && k + 1 < nz) u_up = U(k + 1, cc, pc);
-            const T h = L.wh[k];
-            const T mu = L.mu[k];
-            const T wE = h * cE[o + cc];
-            const T wW = h * cE[o + nb.w];
-            const T wN = h * cN[o + cc];
-            const T wS = h * cN[o + nb.s];
-            const T wU = L.wz[k] * cU[o + cc];
-            const T delta = mu + wE + wW + wN + wS;
-            T r = b[o + cc];
-            if (MODE != SWEEP_ZERO) {
-                const T Hu = mu * u_c + wE * (u_c - U(k, nb.e, pe)) + wW * (u_c - U(k, nb.w, pw)) +
-                             wN * (u_c - U(k, nb.n, pn)) + wS * (u_c - U(k, nb.s, ps)) +
-                             wU * (u_c - u_up) + wD * (u_c - u_dn);
-                r -= Hu;
+        // loads of the CPW cells of this step (wave-uniform validity)
+        SweepRaw<T> R[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int k = k0[c] + t;
+            if (k < nz) {
+                const unsigned sk = (unsigned)k * pstride;
+                R[c].b = bload(T(), rb, oc, sk);
+                R[c].cE = bload(T(), rE, oc, sk);
+                R[c].cEw = bload(T(), rE, ow, sk);
+                R[c].cN = bload(T(), rN, oc, sk);
+                R[c].cNs = bload(T(), rN, os, sk);
+                R[c].cU = bload(T(), rU, oc, sk);
+                R[c].uup = R[c].uE = R[c].uW = R[c].uN = R[c].uS = T(0);
+                if (MODE != SWEEP_ZERO) {
+                    if (k + 1 < nz) R[c].uup = U(k + 1, oc, pc);
+                    R[c].uE = U(k, oe, pe);
+                    R[c].uW = U(k, ow, pw);
+                    R[c].uN = U(k, on, pn);
+                    R[c].uS = U(k, os, ps);
+                }
             }
-            const T e = (t == 0) ? delta + wD : delta + wD * e_prev / (wD + e_prev);
-            const T ip = T(1) / (e + wU);
-            const T g = wU * ip;
-            const T y = (t == 0) ? r : r + g_prev * y_prev;
-            const T eta = (t == 0) ? wD : g_prev * eta_prev;
-            const T cg = (t == 0) ? delta : delta + g_prev * c_prev;
-            su[t] = u_c;
-            sy[t] = y * ip;
-            se[t] = eta * ip;
-            sg[t] = g;
-            sd[t] = cg * ip;
-            e_prev = e;
-            y_prev = y;
-            eta_prev = eta;
-            g_prev = g;
-            c_prev = cg;
-            u_dn = u_c;
-            u_c = u_up;
-            wD = wU;
-        } else {
-            su[t] = 0;
-            sy[t] = 0;
-            se[t] = 0;
-            sg[t] = 0;
-            sd[t] = 0;
+        }
+        // arithmetic
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int k = k0[c] + t;
+            if (k < nz) {
+                const T h = L.wh[k];
+                const T mu = L.mu[k];
+                const T wE = h * R[c].cE;
+                const T wW = h * R[c].cEw;
+                const T wN = h * R[c].cN;
+                const T wS = h * R[c].cNs;
+                const T wU = L.wz[k] * R[c].cU;
+                const T delta = mu + wE + wW + wN + wS;
+                const T uc = u_c[c];
+                T r = R[c].b;
+                if (MODE != SWEEP_ZERO) {
+                    const T Hu = mu * uc + wE * (uc - R[c].uE) + wW * (uc - R[c].uW) + wN * (uc - R[c].uN) +
+                                 wS * (uc - R[c].uS) + wU * (uc - R[c].uup) + wD[c] * (uc - u_dn[c]);
+                    r -= Hu;
+                }
+                const T e = (t == 0) ? delta + wD[c]
+                                     : delta + wD[c] * e_prev[c] * recip(wD[c] + e_prev[c]);
+                const T ip = recip(e + wU);
+                const T g = wU * ip;
+                const T y = (t == 0) ? r : r + g_prev[c] * y_prev[c];
+                const T eta = (t == 0) ? wD[c] : g_prev[c] * eta_prev[c];
+                su[c][t] = uc;
+                sy[c][t] = y * ip;
+                se[c][t] = eta * ip;
+                sg[c][t] = g;
+                if constexpr (kGamma) {
+                    const T cg = (t == 0) ? delta : delta + g_prev[c] * c_prev[c];
+                    sd[c][t] = cg * ip;
+                    c_prev[c] = cg;
+                }
+                e_prev[c] = e;
+                y_prev[c] = y;
+                eta_prev[c] = eta;
+                g_prev[c] = g;
+                u_dn[c] = uc;
+                u_c[c] = R[c].uup;
+                wD[c] = wU;
+            } else {
+                // rows beyond the column: decoupled identity rows (x = 0)
+                su[c][t] = sy[c][t] = se[c][t] = sg[c][t] = T(0);
+                if constexpr (kGamma) sd[c][t] = T(1);
+            }
         }
     }
 
-    // Back substitution inside the chunk: xp, alpha (unit value below), beta
-    // (unit value above) and gamma (row excesses); only the chunk ends of gamma
-    // are kept.
-    T gam_s = 0, gam_e = 0;
-    {
+    // Back substitution inside each chunk: xp, alpha (unit value below), beta
+    // (unit value above) and, in FP32, gamma (row excesses; chunk ends only).
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        T gam_s = 0, gam_e = 0;
         T xn = 0, an = 0, bn = 0, cn = 0;
 #pragma unroll
         for (int t = M - 1; t >= 0; --t) {
-            const T g = sg[t];
-            const T xp = sy[t] + g * xn;
-            const T al = se[t] + g * an;
+            const T g = sg[c][t];
+            const T xp = sy[c][t] + g * xn;
+            const T al = se[c][t] + g * an;
             const T be = (t == M - 1) ? g : g * bn;
-            const T ga = sd[t] + g * cn;
-            if (t == M - 1) gam_e = ga;
-            sy[t] = xp;
-            se[t] = al;
-            sg[t] = be;
+            if constexpr (kGamma) {
+                const T ga = sd[c][t] + g * cn;
+                if (t == M - 1) gam_e = ga;
+                cn = ga;
+            }
+            sy[c][t] = xp;
+            se[c][t] = al;
+            sg[c][t] = be;
             xn = xp;
             an = al;
             bn = be;
-            cn = ga;
         }
-        gam_s = cn;
+        if constexpr (kGamma) {
+            gam_s = cn;
+        } else {
+            gam_s = T(1) - se[c][0] - sg[c][0];
+            gam_e = T(1) - se[c][M - 1] - sg[c][M - 1];
+        }
+        T *rp = red + (size_t)(c * P + p) * 512;
+        rp[lane] = sy[c][0];
+        rp[64 + lane] = se[c][0];
+        rp[128 + lane] = sg[c][0];
+        rp[192 + lane] = gam_s;
+        rp[256 + lane] = sy[c][M - 1];
+        rp[320 + lane] = se[c][M - 1];
+        rp[384 + lane] = sg[c][M - 1];
+        rp[448 + lane] = gam_e;
     }
-
-    T *rp = red + (size_t)p * 512;
-    rp[lane] = sy[0];
-    rp[64 + lane] = se[0];
-    rp[128 + lane] = sg[0];
-    rp[192 + lane] = gam_s;
-    rp[256 + lane] = sy[M - 1];
-    rp[320 + lane] = se[M - 1];
-    rp[384 + lane] = sg[M - 1];
-    rp[448 + lane] = gam_e;
     __syncthreads();
     if (p == 0) {
         // Chunk q, first cell F_q and last cell L_q:
@@ -251,12 +349,12 @@ __global__ __launch_bounds__(1024) void k_sweep(Level<T> L, const T *__restrict_
         // where 1 - as psi = (bs + gs) + as (1 - psi) and 1 - psi is carried
         // by its own positive recurrence.
         T phi = 0, psi = 0, psib = 1;
-        for (int q = 0; q < P; ++q) {
+        for (int q = 0; q < Q; ++q) {
             T *rq = red + (size_t)q * 512;
             const T xs = rq[lane], as = rq[64 + lane], bs = rq[128 + lane], gs = rq[192 + lane];
             const T xe = rq[256 + lane], ae = rq[320 + lane], be = rq[384 + lane], ge = rq[448 + lane];
             const T den = (bs + gs) + as * psib;
-            const T rden = T(1) / den;
+            const T rden = recip(den);
             const T sig = (xs + as * phi) * rden;
             const T tau = bs * rden;
             const T phin = xe + ae * (phi + psi * sig);
@@ -271,7 +369,7 @@ __global__ __launch_bounds__(1024) void k_sweep(Level<T> L, const T *__restrict_
             psib = psibn;
         }
         T Fn = 0;
-        for (int q = P - 1; q >= 0; --q) {
+        for (int q = Q - 1; q >= 0; --q) {
             T *rq = red + (size_t)q * 512;
             const T F = rq[lane] + rq[64 + lane] * Fn;
             const T Lq = rq[128 + lane] + rq[192 + lane] * Fn;
@@ -281,13 +379,19 @@ __global__ __launch_bounds__(1024) void k_sweep(Level<T> L, const T *__restrict_
         }
     }
     __syncthreads();
-    const T xlo = (p > 0) ? red[(size_t)(p - 1) * 512 + 256 + lane] : T(0);
-    const T xhi = (p + 1 < P) ? red[(size_t)(p + 1) * 512 + 320 + lane] : T(0);
-    if (active) {
+    const Rsrc ro = make_rsrc(out, fstride * S);
+    const unsigned oo = active ? oc : 0xFFFFFFFFu;  // inactive lanes write nothing
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int q = c * P + p;
+        const T xlo = (q > 0) ? red[(size_t)(q - 1) * 512 + 256 + lane] : T(0);
+        const T xhi = (q + 1 < Q) ? red[(size_t)(q + 1) * 512 + 320 + lane] : T(0);
 #pragma unroll
         for (int t = 0; t < M; ++t) {
-            const int k = k0 + t;
-            if (k < nz) out[(size_t)k * plane + cc] = su[t] + omega * (sy[t] + se[t] * xlo + sg[t] * xhi);
+            const int k = k0[c] + t;
+            if (k < nz)
+                bstore(su[c][t] + omega * (sy[c][t] + se[c][t] * xlo + sg[c][t] * xhi), ro, oo,
+                       (unsigned)k * pstride);
         }
     }
 }
@@ -307,6 +411,28 @@ __device__ __forceinline__ void stream_coords(const Level<T> &L, int &col, int &
     if (!active) col = 0;
 }
 
+// One stencil row of H: buffer descriptors and lane offsets shared by the
+// streaming kernels (operator apply, residual, CG direction update).
+template <typename T>
+struct StencilRows {
+    Rsrc rE, rN, rU;
+    unsigned oc, oe, ow, on, os, pstride;
+    __device__ StencilRows(const Level<T> &L, unsigned col)
+    {
+        const size_t fstride = (size_t)L.nz * L.plane;
+        rE = make_rsrc(L.c, fstride * sizeof(T));
+        rN = make_rsrc(L.c + fstride, fstride * sizeof(T));
+        rU = make_rsrc(L.c + 2 * fstride, fstride * sizeof(T));
+        const Nbr nb = neighbours(col, L.n, L.plane);
+        oc = col * sizeof(T);
+        oe = nb.e * sizeof(T);
+        ow = nb.w * sizeof(T);
+        on = nb.n * sizeof(T);
+        os = nb.s * sizeof(T);
+        pstride = (unsigned)L.plane * sizeof(T);
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *__restrict__ x,
                                                           T *__restrict__ y)
@@ -314,31 +440,36 @@ __global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *_
     int col, k0;
     bool active;
     stream_coords(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const size_t fstride = (size_t)nz * plane;
-    const T *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    const int nz = L.nz;
+    const StencilRows<T> R(L, col);
+    const size_t fbytes = (size_t)nz * L.plane * sizeof(T);
+    const Rsrc rx = make_rsrc(x, fbytes), ry = make_rsrc(y, fbytes);
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     T xm = 0, wD = 0;
     if (k0 > 0) {
-        xm = x[(size_t)(k0 - 1) * plane + col];
-        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
+        xm = bload(T(), rx, R.oc, sm);
+        wD = L.wz[k0 - 1] * bload(T(), R.rU, R.oc, sm);
     }
-    T xc = x[(size_t)k0 * plane + col];
-#pragma unroll 4
+    T xc = bload(T(), rx, R.oc, (unsigned)k0 * R.pstride);
+#pragma unroll
     for (int t = 0; t < kKChunk; ++t) {
         const int k = k0 + t;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const T xp = (k + 1 < nz) ? x[o + plane + col] : T(0);
-        const T h = L.wh[k];
-        const T wU = L.wz[k] * cU[o + col];
-        const T acc = L.mu[k] * xc + h * cE[o + col] * (xc - x[o + nb.e]) +
-                      h * cE[o + nb.w] * (xc - x[o + nb.w]) + h * cN[o + col] * (xc - x[o + nb.n]) +
-                      h * cN[o + nb.s] * (xc - x[o + nb.s]) + wU * (xc - xp) + wD * (xc - xm);
-        if (active) y[o + col] = acc;
-        xm = xc;
-        xc = xp;
-        wD = wU;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const T xp = (k + 1 < nz) ? bload(T(), rx, R.oc, sk + R.pstride) : T(0);
+            const T h = L.wh[k];
+            const T wU = L.wz[k] * bload(T(), R.rU, R.oc, sk);
+            const T acc = L.mu[k] * xc + h * bload(T(), R.rE, R.oc, sk) * (xc - bload(T(), rx, R.oe, sk)) +
+                          h * bload(T(), R.rE, R.ow, sk) * (xc - bload(T(), rx, R.ow, sk)) +
+                          h * bload(T(), R.rN, R.oc, sk) * (xc - bload(T(), rx, R.on, sk)) +
+                          h * bload(T(), R.rN, R.os, sk) * (xc - bload(T(), rx, R.os, sk)) + wU * (xc - xp) +
+                          wD * (xc - xm);
+            bstore(acc, ry, oo, sk);
+            xm = xc;
+            xc = xp;
+            wD = wU;
+        }
     }
 }
 
@@ -353,6 +484,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
                                                                    const T *__restrict__ b,
                                                                    T *__restrict__ bc)
 {
+    constexpr unsigned S = sizeof(T);
     const int n = L.n, nz = L.nz, plane = L.plane;
     const int nc = n >> 1, planec = nc * nc;
     const int ncb = (planec + kStreamThreads - 1) / kStreamThreads;
@@ -368,14 +500,20 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
     const int ie = (i0 + 2 == n) ? 0 : i0 + 2;
     const int js = (j0 == 0) ? n - 1 : j0 - 1;
     const int jn = (j0 + 2 == n) ? 0 : j0 + 2;
-    // the four children a=(i0,j0) b=(i0+1,j0) c=(i0,j0+1) d=(i0+1,j0+1)
-    const int q[4] = {j0 * n + i0, j0 * n + i0 + 1, (j0 + 1) * n + i0, (j0 + 1) * n + i0 + 1};
-    const int qw0 = j0 * n + iw, qw1 = (j0 + 1) * n + iw;      // west of a, c
-    const int qe0 = j0 * n + ie, qe1 = (j0 + 1) * n + ie;      // east of b, d
-    const int qs0 = js * n + i0, qs1 = js * n + i0 + 1;        // south of a, b
-    const int qn0 = jn * n + i0, qn1 = jn * n + i0 + 1;        // north of c, d
-    const size_t fstride = (size_t)nz * plane;
-    const T *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    // the four children a=(i0,j0) b=(i0+1,j0) c=(i0,j0+1) d=(i0+1,j0+1), byte offsets
+    const unsigned q0 = (j0 * n + i0) * S, q1 = q0 + S, q2 = q0 + n * S, q3 = q2 + S;
+    const unsigned qw0 = (j0 * n + iw) * S, qw1 = qw0 + n * S;   // west of a, c
+    const unsigned qe0 = (j0 * n + ie) * S, qe1 = qe0 + n * S;   // east of b, d
+    const unsigned qs0 = (js * n + i0) * S, qs1 = qs0 + S;       // south of a, b
+    const unsigned qn0 = (jn * n + i0) * S, qn1 = qn0 + S;       // north of c, d
+    const unsigned q[4] = {q0, q1, q2, q3};
+    const size_t fbytes = (size_t)nz * plane * S;
+    const Rsrc ru = make_rsrc(u, fbytes), rb = make_rsrc(b, fbytes);
+    const Rsrc rE = make_rsrc(L.c, fbytes), rN = make_rsrc(L.c + (size_t)nz * plane, fbytes);
+    const Rsrc rU = make_rsrc(L.c + 2 * (size_t)nz * plane, fbytes);
+    const Rsrc rc = make_rsrc(bc, (size_t)nz * planec * S);
+    const unsigned pstride = (unsigned)plane * S, cstride = (unsigned)planec * S;
+    const unsigned oo = active ? (unsigned)ccol * S : 0xFFFFFFFFu;
 
     T um[4], uc[4], wD[4];
 #pragma unroll
@@ -383,39 +521,41 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
         um[a] = 0;
         wD[a] = 0;
         if (k0 > 0) {
-            um[a] = u[(size_t)(k0 - 1) * plane + q[a]];
-            wD[a] = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + q[a]];
+            const unsigned sm = (unsigned)(k0 - 1) * pstride;
+            um[a] = bload(T(), ru, q[a], sm);
+            wD[a] = L.wz[k0 - 1] * bload(T(), rU, q[a], sm);
         }
-        uc[a] = u[(size_t)k0 * plane + q[a]];
+        uc[a] = bload(T(), ru, q[a], (unsigned)k0 * pstride);
     }
-#pragma unroll 2
+#pragma unroll
     for (int t = 0; t < kKChunk; ++t) {
         const int k = k0 + t;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const T h = L.wh[k], mu = L.mu[k], wz = L.wz[k];
-        T up[4], wU[4];
-        T s = 0;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * pstride;
+            const T h = L.wh[k], mu = L.mu[k], wz = L.wz[k];
+            T up[4], wU[4];
+            T s = 0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            up[a] = (k + 1 < nz) ? u[o + plane + q[a]] : T(0);
-            wU[a] = wz * cU[o + q[a]];
-            s += b[o + q[a]] - mu * uc[a] - wU[a] * (uc[a] - up[a]) - wD[a] * (uc[a] - um[a]);
-        }
-        s -= h * cE[o + qw0] * (uc[0] - u[o + qw0]);
-        s -= h * cE[o + qw1] * (uc[2] - u[o + qw1]);
-        s -= h * cE[o + q[1]] * (uc[1] - u[o + qe0]);
-        s -= h * cE[o + q[3]] * (uc[3] - u[o + qe1]);
-        s -= h * cN[o + qs0] * (uc[0] - u[o + qs0]);
-        s -= h * cN[o + qs1] * (uc[1] - u[o + qs1]);
-        s -= h * cN[o + q[2]] * (uc[2] - u[o + qn0]);
-        s -= h * cN[o + q[3]] * (uc[3] - u[o + qn1]);
-        if (active) bc[(size_t)k * planec + ccol] = s;
+            for (int a = 0; a < 4; ++a) {
+                up[a] = (k + 1 < nz) ? bload(T(), ru, q[a], sk + pstride) : T(0);
+                wU[a] = wz * bload(T(), rU, q[a], sk);
+                s += bload(T(), rb, q[a], sk) - mu * uc[a] - wU[a] * (uc[a] - up[a]) - wD[a] * (uc[a] - um[a]);
+            }
+            s -= h * bload(T(), rE, qw0, sk) * (uc[0] - bload(T(), ru, qw0, sk));
+            s -= h * bload(T(), rE, qw1, sk) * (uc[2] - bload(T(), ru, qw1, sk));
+            s -= h * bload(T(), rE, q1, sk) * (uc[1] - bload(T(), ru, qe0, sk));
+            s -= h * bload(T(), rE, q3, sk) * (uc[3] - bload(T(), ru, qe1, sk));
+            s -= h * bload(T(), rN, qs0, sk) * (uc[0] - bload(T(), ru, qs0, sk));
+            s -= h * bload(T(), rN, qs1, sk) * (uc[1] - bload(T(), ru, qs1, sk));
+            s -= h * bload(T(), rN, q2, sk) * (uc[2] - bload(T(), ru, qn0, sk));
+            s -= h * bload(T(), rN, q3, sk) * (uc[3] - bload(T(), ru, qn1, sk));
+            bstore(s, rc, oo, (unsigned)k * cstride);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            um[a] = uc[a];
-            uc[a] = up[a];
-            wD[a] = wU[a];
+            for (int a = 0; a < 4; ++a) {
+                um[a] = uc[a];
+                uc[a] = up[a];
+                wD[a] = wU[a];
+            }
         }
     }
 }
@@ -552,41 +692,49 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     int col, k0;
     bool active;
     stream_coords(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const size_t fstride = (size_t)nz * plane;
-    const double *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    const int nz = L.nz;
+    const StencilRows<double> R(L, col);
+    const size_t n = (size_t)nz * L.plane;
+    const Rsrc rz = z32 ? make_rsrc(z32, n * 4) : make_rsrc(z, n * 8);
+    const Rsrc rp = make_rsrc(p_old, first ? 0 : n * 8);
+    const Rsrc rpn = make_rsrc(p_new, n * 8), rq = make_rsrc(q, n * 8);
+    const bool f32 = z32 != nullptr;
+    const unsigned zs = (unsigned)L.plane * (f32 ? 4u : 8u);
     const double beta = first ? 0.0 : sc->beta;
-    auto PV = [&](size_t idx) -> double {
-        const double zz = z32 ? (double)z32[idx] : z[idx];
-        return first ? zz : zz + beta * p_old[idx];
+    // p_new at (k, lane offset o in bytes of a double)
+    auto PV = [&](int k, unsigned o) -> double {
+        const double zz = f32 ? (double)bload(float(), rz, o >> 1, (unsigned)k * zs)
+                              : bload(double(), rz, o, (unsigned)k * zs);
+        return first ? zz : zz + beta * bload(double(), rp, o, (unsigned)k * R.pstride);
     };
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     double pm = 0, wD = 0;
     if (k0 > 0) {
-        pm = PV((size_t)(k0 - 1) * plane + col);
-        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+        pm = PV(k0 - 1, R.oc);
+        wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, (unsigned)(k0 - 1) * R.pstride);
     }
-    double pc = (k0 < nz) ? PV((size_t)k0 * plane + col) : 0.0;
+    double pc = PV(k0, R.oc);
     double acc_pq = 0;
-#pragma unroll 2
+#pragma unroll
     for (int t = 0; t < kKChunk; ++t) {
         const int k = k0 + t;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const double pp = (k + 1 < nz) ? PV(o + plane + col) : 0.0;
-        const double h = L.wh[k];
-        const double wU = L.wz[k] * cU[o + col];
-        const double qq = L.mu[k] * pc + h * cE[o + col] * (pc - PV(o + nb.e)) +
-                          h * cE[o + nb.w] * (pc - PV(o + nb.w)) + h * cN[o + col] * (pc - PV(o + nb.n)) +
-                          h * cN[o + nb.s] * (pc - PV(o + nb.s)) + wU * (pc - pp) + wD * (pc - pm);
-        if (active) {
-            p_new[o + col] = pc;
-            q[o + col] = qq;
-            acc_pq += pc * qq;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const double pp = (k + 1 < nz) ? PV(k + 1, R.oc) : 0.0;
+            const double h = L.wh[k];
+            const double wU = L.wz[k] * bload(double(), R.rU, R.oc, sk);
+            const double qq = L.mu[k] * pc + h * bload(double(), R.rE, R.oc, sk) * (pc - PV(k, R.oe)) +
+                              h * bload(double(), R.rE, R.ow, sk) * (pc - PV(k, R.ow)) +
+                              h * bload(double(), R.rN, R.oc, sk) * (pc - PV(k, R.on)) +
+                              h * bload(double(), R.rN, R.os, sk) * (pc - PV(k, R.os)) + wU * (pc - pp) +
+                              wD * (pc - pm);
+            bstore(pc, rpn, oo, sk);
+            bstore(qq, rq, oo, sk);
+            if (active) acc_pq += pc * qq;
+            pm = pc;
+            pc = pp;
+            wD = wU;
         }
-        pm = pc;
-        pc = pp;
-        wD = wU;
     }
     double v[1] = {acc_pq};
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
@@ -601,35 +749,39 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
     int col, k0;
     bool active;
     stream_coords(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const size_t fstride = (size_t)nz * plane;
-    const double *cE = L.c, *cN = L.c + fstride, *cU = L.c + 2 * fstride;
+    const int nz = L.nz;
+    const StencilRows<double> R(L, col);
+    const size_t fbytes = (size_t)nz * L.plane * 8;
+    const Rsrc rx = make_rsrc(x, fbytes), rb = make_rsrc(b, fbytes), rr = make_rsrc(r, fbytes);
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     double xm = 0, wD = 0;
     if (k0 > 0) {
-        xm = x[(size_t)(k0 - 1) * plane + col];
-        wD = L.wz[k0 - 1] * cU[(size_t)(k0 - 1) * plane + col];
+        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
+        xm = bload(double(), rx, R.oc, sm);
+        wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, sm);
     }
-    double xc = (k0 < nz) ? x[(size_t)k0 * plane + col] : 0.0;
+    double xc = bload(double(), rx, R.oc, (unsigned)k0 * R.pstride);
     double acc = 0;
+#pragma unroll
     for (int t = 0; t < kKChunk; ++t) {
         const int k = k0 + t;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const double xp = (k + 1 < nz) ? x[o + plane + col] : 0.0;
-        const double h = L.wh[k];
-        const double wU = L.wz[k] * cU[o + col];
-        const double hx = L.mu[k] * xc + h * cE[o + col] * (xc - x[o + nb.e]) +
-                          h * cE[o + nb.w] * (xc - x[o + nb.w]) + h * cN[o + col] * (xc - x[o + nb.n]) +
-                          h * cN[o + nb.s] * (xc - x[o + nb.s]) + wU * (xc - xp) + wD * (xc - xm);
-        if (active) {
-            const double rr = b[o + col] - hx;
-            r[o + col] = rr;
-            acc += rr * rr;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const double xp = (k + 1 < nz) ? bload(double(), rx, R.oc, sk + R.pstride) : 0.0;
+            const double h = L.wh[k];
+            const double wU = L.wz[k] * bload(double(), R.rU, R.oc, sk);
+            const double hx = L.mu[k] * xc + h * bload(double(), R.rE, R.oc, sk) * (xc - bload(double(), rx, R.oe, sk)) +
+                              h * bload(double(), R.rE, R.ow, sk) * (xc - bload(double(), rx, R.ow, sk)) +
+                              h * bload(double(), R.rN, R.oc, sk) * (xc - bload(double(), rx, R.on, sk)) +
+                              h * bload(double(), R.rN, R.os, sk) * (xc - bload(double(), rx, R.os, sk)) +
+                              wU * (xc - xp) + wD * (xc - xm);
+            const double rv = bload(double(), rb, R.oc, sk) - hx;
+            bstore(rv, rr, oo, sk);
+            if (active) acc += rv * rv;
+            xm = xc;
+            xc = xp;
+            wD = wU;
         }
-        xm = xc;
-        xc = xp;
-        wD = wU;
     }
     double v[1] = {acc};
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
@@ -778,57 +930,85 @@ int stream_grid(const Level<T> &L)
     return ncb * nkc;
 }
 
-template <typename T, int M>
-hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega,
-                   int P, hipStream_t s)
+template <typename T, int M, int CPW, int LB>
+hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega, int P,
+                   hipStream_t s)
 {
     const int tiles = (L.plane + 63) / 64;
     const dim3 block(64 * P);
-    const size_t lds = (size_t)P * 512 * sizeof(T);
+    const size_t lds = (size_t)P * CPW * 512 * sizeof(T);
     switch (mode) {
     case SWEEP_ZERO:
-        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_ZERO>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_ZERO, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
         break;
     case SWEEP_GENERAL:
-        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_GENERAL>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_GENERAL, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec,
+                           omega);
         break;
     default:
-        hipLaunchKernelGGL((k_sweep<T, M, SWEEP_PROLONG>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega);
+        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_PROLONG, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec,
+                           omega);
         break;
     }
     return hipGetLastError();
 }
 
+// Launch bound = the smaller of 512/1024 threads that holds the P wavefronts,
+// so each shape gets the largest register budget it can.
+template <typename T, int M, int CPW>
+hipError_t sweep_lb(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega, int P,
+                    hipStream_t s)
+{
+    if (P <= 8) return sweep_m<T, M, CPW, 512>(L, mode, u, b, out, ec, omega, P, s);
+    return sweep_m<T, M, CPW, 1024>(L, mode, u, b, out, ec, omega, P, s);
+}
+
+// Tuning overrides (environment): TPMG_SWEEP_M = cells per chunk (4, 8, 16),
+// TPMG_SWEEP_CPW = chunks per wavefront (1, 2); -1 when unset.
+int env_int(const char *name)
+{
+    const char *v = getenv(name);
+    return v ? atoi(v) : -1;
+}
+
 }  // namespace
 
-bool sweep_shape(int nz, bool fp32, int *M, int *P)
+// Chunking of a column for the sweep: M cells per chunk, CPW chunks per
+// wavefront, P wavefronts (P <= 16).  Default (measured on 1024^2 x 128 in
+// both precisions): one chunk of 16 cells per wavefront.
+bool sweep_shape(int nz, bool fp32, int *M, int *CPW, int *P)
 {
-    const int target = fp32 ? 16 : 8;
-    const int cand[3] = {4, 8, 16};
-    const int want = nz < target ? nz : target;
-    for (int pass = 0; pass < 2; ++pass)
-        for (int m : cand) {
-            if (pass == 0 && m < want) continue;
-            const int p = (nz + m - 1) / m;
-            if (p <= 16) {
-                *M = m;
-                *P = p;
-                return true;
-            }
-        }
-    return false;
+    static const int fm = env_int("TPMG_SWEEP_M"), fc = env_int("TPMG_SWEEP_CPW");
+    (void)fp32;
+    int c = (fc == 1 || fc == 2) ? fc : 1;
+    int m = (fm == 4 || fm == 8 || fm == 16) ? fm : 16;
+    if (m == 16) c = 1;  // (16, 2) is not instantiated: too many registers
+    // short columns: the smallest chunk that still covers them
+    while (m > 4 && (m / 2) * c >= nz) m /= 2;
+    const int p = (nz + m * c - 1) / (m * c);
+    if (p > 16) return false;
+    *M = m;
+    *CPW = c;
+    *P = p;
+    return true;
 }
 
 template <typename T>
-hipError_t launch_sweep(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec,
-                        T omega, hipStream_t s)
+hipError_t launch_sweep(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega,
+                        hipStream_t s)
 {
-    int M = 0, P = 0;
-    if (!sweep_shape(L.nz, sizeof(T) == 4, &M, &P)) return hipErrorInvalidValue;
+    int M = 0, CPW = 0, P = 0;
+    if (!sweep_shape(L.nz, sizeof(T) == 4, &M, &CPW, &P)) return hipErrorInvalidValue;
+    if (CPW == 2) {
+        switch (M) {
+        case 4: return sweep_lb<T, 4, 2>(L, mode, u, b, out, ec, omega, P, s);
+        default: return sweep_lb<T, 8, 2>(L, mode, u, b, out, ec, omega, P, s);
+        }
+    }
     switch (M) {
-    case 4: return sweep_m<T, 4>(L, mode, u, b, out, ec, omega, P, s);
-    case 8: return sweep_m<T, 8>(L, mode, u, b, out, ec, omega, P, s);
-    default: return sweep_m<T, 16>(L, mode, u, b, out, ec, omega, P, s);
+    case 4: return sweep_lb<T, 4, 1>(L, mode, u, b, out, ec, omega, P, s);
+    case 8: return sweep_lb<T, 8, 1>(L, mode, u, b, out, ec, omega, P, s);
+    default: return sweep_lb<T, 16, 1>(L, mode, u, b, out, ec, omega, P, s);
     }
 }
 
