@@ -112,6 +112,15 @@ def probe(tp, torch, w, c, b, kw, args):
             ms = e0.elapsed_time(e1) / args.steps
             res[f"{tag}_{name}_ms"] = ms
             res[f"{tag}_{name}_GBps"] = words * S * w.dof / (ms * 1e-3) / 1e9
+    # CG kernels and the V-cycle inside a profiled mixed solve (HIP events)
+    from paper_1605_00492_amd.binding import K_PCG_APPLY, K_PCG_UPDATE, K_VCYCLE
+    H.solve(b, rtol=w.rtol)
+    H.profile_enable(True)
+    H.solve(b, rtol=w.rtol)
+    for name, cls in (("pcg_apply", K_PCG_APPLY), ("pcg_update", K_PCG_UPDATE), ("vcycle_fp32", K_VCYCLE)):
+        ms, cnt = H.profile_read(cls)
+        res[f"{name}_ms"] = ms / max(cnt, 1)
+    H.profile_enable(False)
     nbytes = 1 << 30
     src = torch.ones(nbytes // 4, dtype=torch.float32, device=c.device)
     dst = torch.empty_like(src)

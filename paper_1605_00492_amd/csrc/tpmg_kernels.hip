@@ -843,9 +843,18 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
 {
     __shared__ double sh[2][1024];
     for (int v = 0; v < nvals; ++v) {
-        double s = 0;
-        for (int i = threadIdx.x; i < G; i += 1024) s += partials[(size_t)v * G + i];
-        sh[v][threadIdx.x] = s;
+        // four independent accumulators (fixed order for a given G)
+        const double *pv = partials + (size_t)v * G;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int i = threadIdx.x;
+        for (; i + 3 * 1024 < G; i += 4 * 1024) {
+            s0 += pv[i];
+            s1 += pv[i + 1024];
+            s2 += pv[i + 2048];
+            s3 += pv[i + 3072];
+        }
+        for (; i < G; i += 1024) s0 += pv[i];
+        sh[v][threadIdx.x] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {

@@ -89,3 +89,15 @@ def closed_form_solve(b, a_h, a_z, c0):
 
 def random_coeffs(rng, n, nz, lo=1.0, hi=1.5):
     return rng.uniform(lo, hi, size=(3, nz, n, n))
+
+
+def patch(field, i, j, size=3, lo=1):
+    """The periodic size x size block of columns starting at (i - lo, j - lo)
+    of a (..., nz, n, n) field.  With size 3 (lo 1) the block holds every
+    stencil input of column (i, j): its four neighbours and the faces between;
+    with size 4 (lo 1) at (2I, 2J) it holds every input of the residual of
+    the four children of coarse column (I, J)."""
+    n = field.shape[-1]
+    ii = (np.arange(size) + i - lo) % n
+    jj = (np.arange(size) + j - lo) % n
+    return field[..., jj[:, None], ii[None, :]]
