@@ -156,6 +156,133 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
 // The per-lane state (u, xp, alpha, beta[, gamma] for CPW x M cells) stays in
 // registers; loads use buffer descriptors with a per-k scalar offset.
 // ---------------------------------------------------------------------------
+// Elimination state of one chunk of one column (one lane): the chunk's
+// forward-eliminated right-hand side sy, the responses se / sg to a unit
+// value just below / above the chunk and, in FP32, sd = T^{-1} delta.
+template <typename T, int M>
+struct ChunkState {
+    static constexpr bool kGamma = sizeof(T) == 4;
+    T sy[M], se[M], sg[M], sd[kGamma ? M : 1];
+    T e_prev, y_prev, eta_prev, g_prev, c_prev;
+
+    __device__ __forceinline__ void init()
+    {
+        e_prev = T(1);
+        y_prev = eta_prev = g_prev = c_prev = T(0);
+    }
+    // Cell t of the chunk: residual r, diagonal excess delta (mass plus
+    // horizontal couplings), couplings wU above and wD below.
+    __device__ __forceinline__ void step(int t, T r, T delta, T wU, T wD)
+    {
+        const T e = (t == 0) ? delta + wD : delta + wD * e_prev * recip(wD + e_prev);
+        const T ip = recip(e + wU);
+        const T g = wU * ip;
+        const T y = (t == 0) ? r : r + g_prev * y_prev;
+        const T eta = (t == 0) ? wD : g_prev * eta_prev;
+        sy[t] = y * ip;
+        se[t] = eta * ip;
+        sg[t] = g;
+        if constexpr (kGamma) {
+            const T cg = (t == 0) ? delta : delta + g_prev * c_prev;
+            sd[t] = cg * ip;
+            c_prev = cg;
+        }
+        e_prev = e;
+        y_prev = y;
+        eta_prev = eta;
+        g_prev = g;
+    }
+    // rows beyond the column: decoupled identity rows (x = 0)
+    __device__ __forceinline__ void identity(int t)
+    {
+        sy[t] = se[t] = sg[t] = T(0);
+        if constexpr (kGamma) sd[t] = T(1);
+    }
+    // Back substitution inside the chunk: xp, alpha (unit value below), beta
+    // (unit value above) and, in FP32, gamma (row excesses; chunk ends only).
+    // Then the chunk-end values go to rp[8][64] for the coupling system.
+    __device__ __forceinline__ void backsub_publish(T *rp, int lane)
+    {
+        T gam_s = 0, gam_e = 0;
+        T xn = 0, an = 0, bn = 0, cn = 0;
+#pragma unroll
+        for (int t = M - 1; t >= 0; --t) {
+            const T g = sg[t];
+            const T xp = sy[t] + g * xn;
+            const T al = se[t] + g * an;
+            const T be = (t == M - 1) ? g : g * bn;
+            if constexpr (kGamma) {
+                const T ga = sd[t] + g * cn;
+                if (t == M - 1) gam_e = ga;
+                cn = ga;
+            }
+            sy[t] = xp;
+            se[t] = al;
+            sg[t] = be;
+            xn = xp;
+            an = al;
+            bn = be;
+        }
+        if constexpr (kGamma) {
+            gam_s = cn;
+        } else {
+            gam_s = T(1) - se[0] - sg[0];
+            gam_e = T(1) - se[M - 1] - sg[M - 1];
+        }
+        rp[lane] = sy[0];
+        rp[64 + lane] = se[0];
+        rp[128 + lane] = sg[0];
+        rp[192 + lane] = gam_s;
+        rp[256 + lane] = sy[M - 1];
+        rp[320 + lane] = se[M - 1];
+        rp[384 + lane] = sg[M - 1];
+        rp[448 + lane] = gam_e;
+    }
+    // Chunk solution at cell t given the cells just below / above the chunk.
+    __device__ __forceinline__ T value(int t, T xlo, T xhi) const { return sy[t] + se[t] * xlo + sg[t] * xhi; }
+};
+
+// The system coupling the chunks of one column (lane), solved by one
+// wavefront.  Chunk q, first cell F_q and last cell L_q:
+//   F_q = xs + as L_{q-1} + bs F_{q+1},   L_q = xe + ae L_{q-1} + be F_{q+1}.
+// Forward over chunks with L_{q-1} = phi + psi F_q gives
+//   F_q = sig + tau F_{q+1},  L_q = phi' + psi' F_{q+1},
+// where 1 - as psi = (bs + gs) + as (1 - psi) and 1 - psi is carried by its
+// own positive recurrence.  On return red[q][4][.] = L_q, red[q][5][.] = F_q.
+template <typename T>
+__device__ __forceinline__ void coupling_solve(T *red, int Q, int lane)
+{
+    T phi = 0, psi = 0, psib = 1;
+    for (int q = 0; q < Q; ++q) {
+        T *rq = red + (size_t)q * 512;
+        const T xs = rq[lane], as = rq[64 + lane], bs = rq[128 + lane], gs = rq[192 + lane];
+        const T xe = rq[256 + lane], ae = rq[320 + lane], be = rq[384 + lane], ge = rq[448 + lane];
+        const T den = (bs + gs) + as * psib;
+        const T rden = recip(den);
+        const T sig = (xs + as * phi) * rden;
+        const T tau = bs * rden;
+        const T phin = xe + ae * (phi + psi * sig);
+        const T psin = be + ae * psi * tau;
+        const T psibn = ge + ae * (psib + psi * gs) * rden;
+        rq[lane] = sig;
+        rq[64 + lane] = tau;
+        rq[128 + lane] = phin;
+        rq[192 + lane] = psin;
+        phi = phin;
+        psi = psin;
+        psib = psibn;
+    }
+    T Fn = 0;
+    for (int q = Q - 1; q >= 0; --q) {
+        T *rq = red + (size_t)q * 512;
+        const T F = rq[lane] + rq[64 + lane] * Fn;
+        const T Lq = rq[128 + lane] + rq[192 + lane] * Fn;
+        rq[256 + lane] = Lq;
+        rq[320 + lane] = F;
+        Fn = F;
+    }
+}
+
 template <typename T>
 struct SweepRaw {
     T uup, uE, uW, uN, uS, b, cE, cEw, cN, cNs, cU;
@@ -179,7 +306,6 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
                                               T *__restrict__ out, const T *__restrict__ ec, T omega,
                                               int tbi, int tbj)
 {
-    constexpr bool kGamma = sizeof(T) == 4;
     constexpr unsigned S = sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *red = reinterpret_cast<T *>(smem_raw);  // [Q][8][64]
@@ -221,8 +347,9 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
         return v;
     };
 
-    T su[CPW][M], sy[CPW][M], se[CPW][M], sg[CPW][M], sd[CPW][kGamma ? M : 1];
-    T u_dn[CPW], u_c[CPW], wD[CPW], e_prev[CPW], y_prev[CPW], eta_prev[CPW], g_prev[CPW], c_prev[CPW];
+    ChunkState<T, M> cs[CPW];
+    T su[CPW][M];
+    T u_dn[CPW], u_c[CPW], wD[CPW];
     int k0[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -235,8 +362,7 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
             }
             if (MODE != SWEEP_ZERO) u_c[c] = U(k0[c], oc, pc);
         }
-        e_prev[c] = T(1);
-        y_prev[c] = eta_prev[c] = g_prev[c] = c_prev[c] = T(0);
+        cs[c].init();
     }
 
 #pragma unroll
@@ -284,114 +410,22 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
                                  wS * (uc - R[c].uS) + wU * (uc - R[c].uup) + wD[c] * (uc - u_dn[c]);
                     r -= Hu;
                 }
-                const T e = (t == 0) ? delta + wD[c]
-                                     : delta + wD[c] * e_prev[c] * recip(wD[c] + e_prev[c]);
-                const T ip = recip(e + wU);
-                const T g = wU * ip;
-                const T y = (t == 0) ? r : r + g_prev[c] * y_prev[c];
-                const T eta = (t == 0) ? wD[c] : g_prev[c] * eta_prev[c];
+                cs[c].step(t, r, delta, wU, wD[c]);
                 su[c][t] = uc;
-                sy[c][t] = y * ip;
-                se[c][t] = eta * ip;
-                sg[c][t] = g;
-                if constexpr (kGamma) {
-                    const T cg = (t == 0) ? delta : delta + g_prev[c] * c_prev[c];
-                    sd[c][t] = cg * ip;
-                    c_prev[c] = cg;
-                }
-                e_prev[c] = e;
-                y_prev[c] = y;
-                eta_prev[c] = eta;
-                g_prev[c] = g;
                 u_dn[c] = uc;
                 u_c[c] = R[c].uup;
                 wD[c] = wU;
             } else {
-                // rows beyond the column: decoupled identity rows (x = 0)
-                su[c][t] = sy[c][t] = se[c][t] = sg[c][t] = T(0);
-                if constexpr (kGamma) sd[c][t] = T(1);
+                cs[c].identity(t);
+                su[c][t] = T(0);
             }
         }
     }
 
-    // Back substitution inside each chunk: xp, alpha (unit value below), beta
-    // (unit value above) and, in FP32, gamma (row excesses; chunk ends only).
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-        T gam_s = 0, gam_e = 0;
-        T xn = 0, an = 0, bn = 0, cn = 0;
-#pragma unroll
-        for (int t = M - 1; t >= 0; --t) {
-            const T g = sg[c][t];
-            const T xp = sy[c][t] + g * xn;
-            const T al = se[c][t] + g * an;
-            const T be = (t == M - 1) ? g : g * bn;
-            if constexpr (kGamma) {
-                const T ga = sd[c][t] + g * cn;
-                if (t == M - 1) gam_e = ga;
-                cn = ga;
-            }
-            sy[c][t] = xp;
-            se[c][t] = al;
-            sg[c][t] = be;
-            xn = xp;
-            an = al;
-            bn = be;
-        }
-        if constexpr (kGamma) {
-            gam_s = cn;
-        } else {
-            gam_s = T(1) - se[c][0] - sg[c][0];
-            gam_e = T(1) - se[c][M - 1] - sg[c][M - 1];
-        }
-        T *rp = red + (size_t)(c * P + p) * 512;
-        rp[lane] = sy[c][0];
-        rp[64 + lane] = se[c][0];
-        rp[128 + lane] = sg[c][0];
-        rp[192 + lane] = gam_s;
-        rp[256 + lane] = sy[c][M - 1];
-        rp[320 + lane] = se[c][M - 1];
-        rp[384 + lane] = sg[c][M - 1];
-        rp[448 + lane] = gam_e;
-    }
+    for (int c = 0; c < CPW; ++c) cs[c].backsub_publish(red + (size_t)(c * P + p) * 512, lane);
     __syncthreads();
-    if (p == 0) {
-        // Chunk q, first cell F_q and last cell L_q:
-        //   F_q = xs + as L_{q-1} + bs F_{q+1},   L_q = xe + ae L_{q-1} + be F_{q+1}.
-        // Forward over chunks with L_{q-1} = phi + psi F_q gives
-        //   F_q = sig + tau F_{q+1},  L_q = phi' + psi' F_{q+1},
-        // where 1 - as psi = (bs + gs) + as (1 - psi) and 1 - psi is carried
-        // by its own positive recurrence.
-        T phi = 0, psi = 0, psib = 1;
-        for (int q = 0; q < Q; ++q) {
-            T *rq = red + (size_t)q * 512;
-            const T xs = rq[lane], as = rq[64 + lane], bs = rq[128 + lane], gs = rq[192 + lane];
-            const T xe = rq[256 + lane], ae = rq[320 + lane], be = rq[384 + lane], ge = rq[448 + lane];
-            const T den = (bs + gs) + as * psib;
-            const T rden = recip(den);
-            const T sig = (xs + as * phi) * rden;
-            const T tau = bs * rden;
-            const T phin = xe + ae * (phi + psi * sig);
-            const T psin = be + ae * psi * tau;
-            const T psibn = ge + ae * (psib + psi * gs) * rden;
-            rq[lane] = sig;
-            rq[64 + lane] = tau;
-            rq[128 + lane] = phin;
-            rq[192 + lane] = psin;
-            phi = phin;
-            psi = psin;
-            psib = psibn;
-        }
-        T Fn = 0;
-        for (int q = Q - 1; q >= 0; --q) {
-            T *rq = red + (size_t)q * 512;
-            const T F = rq[lane] + rq[64 + lane] * Fn;
-            const T Lq = rq[128 + lane] + rq[192 + lane] * Fn;
-            rq[256 + lane] = Lq;
-            rq[320 + lane] = F;
-            Fn = F;
-        }
-    }
+    if (p == 0) coupling_solve(red, Q, lane);
     __syncthreads();
     const Rsrc ro = make_rsrc(out, fstride * S);
     const unsigned oo = active ? oc : 0xFFFFFFFFu;  // inactive lanes write nothing
@@ -403,9 +437,7 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int k = k0[c] + t;
-            if (k < nz)
-                bstore(su[c][t] + omega * (sy[c][t] + se[c][t] * xlo + sg[c][t] * xhi), ro, oo,
-                       (unsigned)k * pstride);
+            if (k < nz) bstore(su[c][t] + omega * cs[c].value(t, xlo, xhi), ro, oo, (unsigned)k * pstride);
         }
     }
 }
