@@ -55,7 +55,7 @@ enum FinalizeStage : int {
 };
 
 // Upper bound on per-dot partial sums (one per workgroup) in any reduction.
-constexpr int kMaxPartials = 1 << 17;
+constexpr int kMaxPartials = 1 << 19;
 
 // ---- launchers (kernels.hip) --------------------------------------------
 // Each returns the launch status.  Shapes are validated by the caller.

@@ -14,6 +14,7 @@
 //    into P chunks of M cells, one wavefront per chunk, each chunk eliminated
 //    locally and the P chunks coupled through a small system in LDS.
 #include <cstdlib>
+#include <type_traits>
 
 #include "tpmg_internal.h"
 
@@ -23,7 +24,6 @@ namespace {
 
 constexpr int kXcds = 8;
 constexpr int kStreamThreads = 256;
-constexpr int kKChunk = 16;  // cells along k per thread in the streaming kernels
 constexpr double kDblMax = 1.7976931348623157e308;
 
 // Workgroups are dispatched to the XCDs round-robin.  Renumber them so that
@@ -443,16 +443,16 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// y = H x on one level.  Thread = (column, chunk of kKChunk cells).
+// y = H x on one level.  Thread = (column, chunk of KC cells along k).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <int KC, typename T>
 __device__ __forceinline__ void stream_coords(const Level<T> &L, int &col, int &k0, bool &active)
 {
     const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int kc = blk / ncb, cb = blk % ncb;
     col = cb * kStreamThreads + threadIdx.x;
-    k0 = kc * kKChunk;
+    k0 = kc * KC;
     active = col < L.plane;
     if (!active) col = 0;
 }
@@ -479,13 +479,13 @@ struct StencilRows {
     }
 };
 
-template <typename T>
+template <typename T, int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *__restrict__ x,
                                                           T *__restrict__ y)
 {
     int col, k0;
     bool active;
-    stream_coords(L, col, k0, active);
+    stream_coords<KC>(L, col, k0, active);
     const int nz = L.nz;
     const StencilRows<T> R(L, col);
     const size_t fbytes = (size_t)nz * L.plane * sizeof(T);
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *_
     }
     T xc = bload(T(), rx, R.oc, (unsigned)k0 * R.pstride);
 #pragma unroll
-    for (int t = 0; t < kKChunk; ++t) {
+    for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
             const unsigned sk = (unsigned)k * R.pstride;
@@ -523,9 +523,9 @@ __global__ __launch_bounds__(kStreamThreads) void k_apply(Level<T> L, const T *_
 // b_c = R (b - H u): residual on the fine level summed over the four children
 // of each coarse cell (Sec. 3.2).  Couplings between the four children cancel
 // in the sum, so only the eight outer horizontal faces and the vertical faces
-// enter.  Thread = (coarse column, chunk of kKChunk cells).
+// enter.  Thread = (coarse column, chunk of KC cells).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, const T *__restrict__ u,
                                                                    const T *__restrict__ b,
                                                                    T *__restrict__ bc)
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
     int ccol = cb * kStreamThreads + threadIdx.x;
     const bool active = ccol < planec;
     if (!active) ccol = 0;
-    const int k0 = kc * kKChunk;
+    const int k0 = kc * KC;
     const int I = ccol % nc, J = ccol / nc;
     const int i0 = 2 * I, j0 = 2 * J;
     const int iw = (i0 == 0) ? n - 1 : i0 - 1;
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
         uc[a] = bload(T(), ru, q[a], (unsigned)k0 * pstride);
     }
 #pragma unroll
-    for (int t = 0; t < kKChunk; ++t) {
+    for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
             const unsigned sk = (unsigned)k * pstride;
@@ -727,6 +727,7 @@ __global__ __launch_bounds__(256) void k_faces_to_column(const double *__restric
 // p_new = z + beta p_old (p_new = z on the first iteration), q = H p_new, and
 // partial sums of (p_new, q).  Neighbour values of p_new are formed on the fly
 // from z and p_old, so p_old and p_new must be different buffers.
+template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const double *__restrict__ z,
                                                               const float *__restrict__ z32,
                                                               const double *__restrict__ p_old,
@@ -737,7 +738,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
 {
     int col, k0;
     bool active;
-    stream_coords(L, col, k0, active);
+    stream_coords<KC>(L, col, k0, active);
     const int nz = L.nz;
     const StencilRows<double> R(L, col);
     const size_t n = (size_t)nz * L.plane;
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     double pc = PV(k0, R.oc);
     double acc_pq = 0;
 #pragma unroll
-    for (int t = 0; t < kKChunk; ++t) {
+    for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
             const unsigned sk = (unsigned)k * R.pstride;
@@ -787,6 +788,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
 }
 
 // r = b - H x, and partial sums of (r, r).
+template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, const double *__restrict__ x,
                                                              const double *__restrict__ b,
                                                              double *__restrict__ r,
@@ -794,7 +796,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
 {
     int col, k0;
     bool active;
-    stream_coords(L, col, k0, active);
+    stream_coords<KC>(L, col, k0, active);
     const int nz = L.nz;
     const StencilRows<double> R(L, col);
     const size_t fbytes = (size_t)nz * L.plane * 8;
@@ -809,7 +811,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
     double xc = bload(double(), rx, R.oc, (unsigned)k0 * R.pstride);
     double acc = 0;
 #pragma unroll
-    for (int t = 0; t < kKChunk; ++t) {
+    for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
             const unsigned sk = (unsigned)k * R.pstride;
@@ -929,6 +931,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
 }
 
 // dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q) on level-0 faces.
+template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> L,
                                                                   const double *__restrict__ lam,
                                                                   const double *__restrict__ x,
@@ -936,13 +939,13 @@ __global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> 
 {
     int col, k0;
     bool active;
-    stream_coords(L, col, k0, active);
+    stream_coords<KC>(L, col, k0, active);
     const int nz = L.nz, plane = L.plane;
     const Nbr nb = neighbours(col, L.n, plane);
     const size_t fstride = (size_t)nz * plane;
     double lc = (k0 < nz) ? lam[(size_t)k0 * plane + col] : 0.0;
     double xc = (k0 < nz) ? x[(size_t)k0 * plane + col] : 0.0;
-    for (int t = 0; t < kKChunk; ++t) {
+    for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k >= nz) break;
         const size_t o = (size_t)k * plane;
@@ -963,10 +966,13 @@ __global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> 
 }
 
 // Streaming copy with 16-byte accesses: the bandwidth reference point.
-__global__ __launch_bounds__(256) void k_probe_copy(const uint4 *__restrict__ s, uint4 *__restrict__ d,
-                                                    size_t n)
+// One 16-byte element per thread, non-temporal: the fastest plain copy
+// measured on MI355X (more elements per thread lowered the rate).
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_probe_copy(const v4u *__restrict__ s, v4u *__restrict__ d, size_t n)
 {
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) d[g] = s[g];
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(s + g), d + g);
 }
 
 int grid_for(size_t n, int per_thread = 4)
@@ -977,21 +983,39 @@ int grid_for(size_t n, int per_thread = 4)
     return (int)g;
 }
 
-template <typename T>
-int stream_grid(const Level<T> &L)
-{
-    const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
-    const int nkc = (L.nz + kKChunk - 1) / kKChunk;
-    return ncb * nkc;
-}
-
 // Tuning overrides (environment): TPMG_SWEEP_M = cells per chunk (4, 8, 16),
 // TPMG_SWEEP_CPW = chunks per wavefront (1, 2), TPMG_SWEEP_BI / _BJ = tile
-// block shape; -1 when unset.
+// block shape, TPMG_KCHUNK = cells along k per thread of the streaming
+// kernels (4, 8, 16); -1 when unset.
 int env_int(const char *name)
 {
     const char *v = getenv(name);
     return v ? atoi(v) : -1;
+}
+
+int stream_kc()
+{
+    static const int e = env_int("TPMG_KCHUNK");
+    return (e == 4 || e == 8 || e == 16) ? e : 16;
+}
+
+template <typename T>
+int stream_grid(const Level<T> &L, int kc)
+{
+    const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
+    const int nkc = (L.nz + kc - 1) / kc;
+    return ncb * nkc;
+}
+
+// Calls f(std::integral_constant<int, KC>) for the k-chunk length kc.
+template <class F>
+hipError_t with_kc(int kc, F f)
+{
+    switch (kc) {
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    default: return f(std::integral_constant<int, 16>());
+    }
 }
 
 template <typename T, int M, int CPW, int LB>
@@ -1076,8 +1100,12 @@ hipError_t launch_sweep(const Level<T> &L, int mode, const T *u, const T *b, T *
 template <typename T>
 hipError_t launch_apply(const Level<T> &L, const T *x, T *y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_apply<T>, dim3(stream_grid(L)), dim3(kStreamThreads), 0, s, L, x, y);
-    return hipGetLastError();
+    const int kc = stream_kc();
+    return with_kc(kc, [&](auto KCc) {
+        hipLaunchKernelGGL((k_apply<T, decltype(KCc)::value>), dim3(stream_grid(L, kc)), dim3(kStreamThreads), 0, s,
+                           L, x, y);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -1085,9 +1113,13 @@ hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *b
 {
     const int planec = (L.n / 2) * (L.n / 2);
     const int ncb = (planec + kStreamThreads - 1) / kStreamThreads;
-    const int nkc = (L.nz + kKChunk - 1) / kKChunk;
-    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(ncb * nkc), dim3(kStreamThreads), 0, s, L, u, b, bc);
-    return hipGetLastError();
+    const int kc = stream_kc();
+    const int nkc = (L.nz + kc - 1) / kc;
+    return with_kc(kc, [&](auto KCc) {
+        hipLaunchKernelGGL((k_resid_restrict<T, decltype(KCc)::value>), dim3(ncb * nkc), dim3(kStreamThreads), 0, s,
+                           L, u, b, bc);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -1180,20 +1212,27 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
                             double *p_new, double *q, const Scalars *sc, int first, double *partials,
                             int *nblocks_out, hipStream_t s)
 {
-    const int G = stream_grid(L);
+    const int kc = stream_kc();
+    const int G = stream_grid(L, kc);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_pcg_apply, dim3(G), dim3(kStreamThreads), 0, s, L, z, z32, p_old, p_new, q, sc, first,
-                       partials);
-    return hipGetLastError();
+    return with_kc(kc, [&](auto KCc) {
+        hipLaunchKernelGGL((k_pcg_apply<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, z, z32, p_old,
+                           p_new, q, sc, first, partials);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
                            double *partials, int *nblocks_out, hipStream_t s)
 {
-    const int G = stream_grid(L);
+    const int kc = stream_kc();
+    const int G = stream_grid(L, kc);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_residual, dim3(G), dim3(kStreamThreads), 0, s, L, x, b, r, partials);
-    return hipGetLastError();
+    return with_kc(kc, [&](auto KCc) {
+        hipLaunchKernelGGL((k_residual<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b, r,
+                           partials);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q, float *r32,
@@ -1225,14 +1264,20 @@ hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scala
 hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x, double *g,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_face_gradient, dim3(stream_grid(L)), dim3(kStreamThreads), 0, s, L, lam, x, g);
-    return hipGetLastError();
+    const int kc = stream_kc();
+    return with_kc(kc, [&](auto KCc) {
+        hipLaunchKernelGGL((k_face_gradient<decltype(KCc)::value>), dim3(stream_grid(L, kc)), dim3(kStreamThreads), 0,
+                           s, L, lam, x, g);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(n, 8)), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
+    size_t g = (n + 255) / 256;
+    if (g > (1u << 30)) g = 1u << 30;
+    hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)g), dim3(256), 0, s, (const v4u *)src, (v4u *)dst, n);
     return hipGetLastError();
 }
 
