@@ -234,6 +234,19 @@ def main():
     Hm.close()
     H64.close()
 
+    # Achievable HBM rate on this GPU: a plain 1 GiB device copy (library kernel).
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    tp.bandwidth_probe(dst, src)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        tp.bandwidth_probe(dst, src)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes / ((time.perf_counter() - t1) / 20) / 1e9
+    del src, dst
+
     traffic = measured_traffic(w.dof)
     out = {
         "metric": "time per solve to 1e-8 rel. residual (DOF/s, % HBM peak), FP32-MG vs FP64",
@@ -263,7 +276,10 @@ def main():
             "forward_iterations": r["info"]["iterations"], "adjoint_iterations": r["info_adj"]["iterations"],
         },
         "vcycle_fp32": {"ms": vc_avg_s * 1e3, "model_bytes_per_dof": VCYCLE_WORDS * 4,
-                        "model_GBps": vc_gbs, "frac_hbm_peak": vc_gbs / HBM_PEAK_GBS},
+                        "model_GBps": vc_gbs, "frac_hbm_peak": vc_gbs / HBM_PEAK_GBS,
+                        "frac_of_copy": vc_gbs / copy_gbs},
+        "stream": {"copy_GBps": copy_gbs, "copy_frac_hbm_peak": copy_gbs / HBM_PEAK_GBS,
+                   "sweep_frac_of_copy": achieved / copy_gbs},
         "roofline": {"kernel": "k_sweep<float> finest level (general sweep)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
