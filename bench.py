@@ -142,6 +142,69 @@ def probe(tp, torch, w, c, b, kw, args):
     H.close()
 
 
+def robustness(tp, torch, w, dev, args):
+    """Sec. 5.2 robustness study on the GPU (mixed precision, rtol 1e-8).
+
+    PCG iterations and solve time against the Courant number, with the
+    horizontal coupling a_h = (nu_CFL / 2)^2 on the workload's grid, and
+    against the horizontal resolution at nu_CFL = 8, for: the single-level
+    method (two line-Jacobi sweeps per iteration), multigrid with three fewer
+    levels (coarsest grid n/2^(L-4)) and two or sixteen coarse sweeps,
+    multigrid to a 16 x 16 coarsest grid with two (the default) or sixteen
+    coarse sweeps, and multigrid down to a single column with an exact
+    coarsest solve."""
+    import numpy as np
+
+    import synthetic as syn
+
+    def variants(n):
+        deep = int(round(np.log2(n))) + 1
+        lv = int(round(np.log2(n // 16))) + 1
+        sh = max(1, lv - 3)   # coarsest grid 8x finer than 16 x 16: a harder coarse problem
+        return [("single_level", dict(levels=1, coarse="smooth", n_coarse=2)),
+                ("mg_shallow_2sweeps", dict(levels=sh, coarse="smooth", n_coarse=2)),
+                ("mg_shallow_16sweeps", dict(levels=sh, coarse="smooth", n_coarse=16)),
+                ("mg_16x16_2sweeps", dict(levels=lv, coarse="smooth", n_coarse=2)),
+                ("mg_16x16_16sweeps", dict(levels=lv, coarse="smooth", n_coarse=16)),
+                ("mg_1x1_direct", dict(levels=deep, coarse="direct"))]
+
+    def run(ww, a_h, names):
+        c = torch.from_numpy(ww.coefficients()).to(dev)
+        b = torch.from_numpy(ww.rhs()).to(dev)
+        rows = []
+        for name, kw in variants(ww.n):
+            if name not in names:
+                continue
+            H = tp.Hierarchy(c, dz=ww.dz(), a_h=a_h, a_z=ww.a_z, nu=ww.nu, omega=ww.omega, precision="mixed",
+                             **kw)
+            H.solve(b, rtol=1e-8, maxit=1000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = H.solve(b, rtol=1e-8, maxit=1000)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            H.close()
+            rows.append(dict(variant=name, n=ww.n, nz=ww.nz, levels=kw["levels"], a_h=a_h,
+                             iterations=info["iterations"], converged=info["converged"],
+                             true_rel_residual=info["true_rel_residual"], solve_ms=ms))
+            log(f"robustness {rows[-1]}")
+        del c, b
+        return rows
+
+    all_names = [v[0] for v in variants(w.n)]
+    out = {"workload": w.name, "a_h_rule": "a_h = (nu_CFL/2)^2", "courant": [], "resolution": []}
+    for nu in (2, 4, 8, 16, 32, 64):
+        for r in run(w, (nu / 2.0) ** 2, all_names):
+            out["courant"].append(dict(nu_cfl=nu, **r))
+    for n in (128, 256, 512, 1024):
+        if n > w.n:
+            break
+        ww = syn.scaled(w, n, levels=int(round(np.log2(n // 16))) + 1, name=f"{w.name}@{n}")
+        for r in run(ww, 16.0, ["mg_16x16_2sweeps", "mg_1x1_direct"]):
+            out["resolution"].append(dict(nu_cfl=8, **r))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +212,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large_1024x1024x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--robustness", action="store_true",
+                    help="Courant-number and resolution study (single level vs multigrid variants)")
     ap.add_argument("--probe", action="store_true",
                     help="only run the finest-level FP32 sweep and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
@@ -166,6 +231,9 @@ def main():
 
     w = syn.CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    if args.robustness:
+        robustness(tp, torch, w, dev, args)
+        return
     log(f"generating {w.name} ({w.dof} DOF)")
     c = torch.from_numpy(w.coefficients()).to(dev)
     b = torch.from_numpy(w.rhs()).to(dev)

@@ -24,6 +24,12 @@ WORKLOADS = {
     "graded_128x128x64": syn.scaled(syn.CONFIGS["fp64_512x512x64"], 128, levels=4),
     "adjoint_256x256x32": syn.CONFIGS["adjoint_256x256x32"],
     "ragged_48x48x13": syn.Workload("ragged_48x48x13", 48, 13, 4, 1.0, 1e3, True, "uniform"),
+    # single-level line-Jacobi preconditioner (two sweeps) at nu_CFL = 8
+    "single_level_64x64x16": syn.Workload("single_level_64x64x16", 64, 16, 1, 16.0, 1e4, True, "uniform",
+                                          coarse="smooth", n_coarse=2),
+    # coarsening down to one column, exact coarsest solve, at nu_CFL = 64
+    "deep_direct_64x64x16": syn.Workload("deep_direct_64x64x16", 64, 16, 7, 1024.0, 1e4, True, "uniform",
+                                         coarse="direct"),
 }
 
 
@@ -70,7 +76,8 @@ def test_mixed_reaches_fp64_accuracy(work, flexible):
           f"(fp64 oracle {work['info_or']['iterations']} it, error {err64:.2e})", flush=True)
     assert rel_err(host(x), work["x_or"]) <= 1e-8
     assert err <= 1.5 * err64 + 1e-10, (err, err64)
-    assert abs(info["iterations"] - work["info_or"]["iterations"]) <= 1
+    it_or = work["info_or"]["iterations"]
+    assert abs(info["iterations"] - it_or) <= max(1, it_or // 20)
     H.close()
 
 

@@ -75,3 +75,45 @@ def test_nonzero_initial_guess_and_zero_rhs():
     assert info["iterations"] <= 1
     z, infoz = P.pcg(np.zeros_like(b), rtol=1e-8)
     assert infoz["converged"] and infoz["iterations"] == 0 and not z.any()
+
+
+def _iterations(c, b, dz, a_h, **kw):
+    P = oracle.Problem(c, a_h=a_h, a_z=1e4, dz=dz, **kw)
+    _, info = P.pcg(b, rtol=1e-8, maxit=400)
+    assert info["converged"]
+    return info["iterations"]
+
+
+def test_courant_number_robustness():
+    """Sec. 5.2 (robustness in the Courant number, a_h = (nu_CFL / 2)^2): the
+    single-level method degrades sharply as nu_CFL grows; multigrid with a
+    fixed coarsest grid (16 x 16, two sweeps) degrades mildly; a stronger
+    coarse solve (more sweeps, or coarsening to one column with an exact
+    solve) removes most of the growth."""
+    n, nz = 64, 16
+    w = syn.Workload("cfl64x64x16", n, nz, 3, 1.0, 1e4, True, "uniform")
+    c, b, dz = w.coefficients(), w.rhs(), w.dz()
+    it = {}
+    for nu in (2, 8, 64):
+        a_h = (nu / 2.0) ** 2
+        it[nu] = dict(
+            single=_iterations(c, b, dz, a_h, levels=1, coarse="smooth", n_coarse=2),
+            mg=_iterations(c, b, dz, a_h, levels=3, coarse="smooth", n_coarse=2),
+            mg16=_iterations(c, b, dz, a_h, levels=3, coarse="smooth", n_coarse=16),
+            deep=_iterations(c, b, dz, a_h, levels=7, coarse="direct"))
+    assert it[64]["single"] >= 4 * it[2]["single"], it
+    for nu in (8, 64):
+        assert 3 * it[nu]["mg"] <= it[nu]["single"], it
+        assert it[nu]["mg16"] < it[nu]["mg"], it
+    assert it[64]["mg16"] <= 0.6 * it[64]["mg"], it
+    assert it[64]["deep"] - it[2]["deep"] <= 2, it
+
+
+def test_resolution_independence_fixed_courant():
+    """Sec. 5.2: at fixed nu_CFL = 8 the multigrid iteration count does not grow
+    with the horizontal resolution (coarsest grid 16 x 16 throughout)."""
+    its = []
+    for n, levels in [(32, 2), (64, 3), (128, 4)]:
+        w = syn.Workload(f"res{n}", n, 16, levels, 16.0, 1e4, True, "uniform")
+        its.append(_iterations(w.coefficients(), w.rhs(), w.dz(), 16.0, levels=levels))
+    assert its[2] <= its[1] <= its[0], its
