@@ -172,7 +172,7 @@ size_t plan_workspace(const tpmg_desc &d, tpmg_hierarchy *h)
     double *stage = (double *)take(3 * ncell * sizeof(double));
     float *r32 = mixed ? (float *)take(ncell * sizeof(float)) : nullptr;
     float *z32 = mixed ? (float *)take(ncell * sizeof(float)) : nullptr;
-    double *partials = (double *)take(2 * (size_t)kMaxPartials * sizeof(double));
+    double *partials = (double *)take((2 * (size_t)kMaxPartials + 2 * kReduceSegs) * sizeof(double));
     Scalars *sc = (Scalars *)take(sizeof(Scalars));
     int *bad = (int *)take(sizeof(int) * 4);
     if (h) {
@@ -433,7 +433,8 @@ tpmg_status check_ptrs(const tpmg_hierarchy *h, std::initializer_list<const void
 // Reduce the partials of the last launch into the scalars.
 tpmg_status finalize(tpmg_hierarchy *h, int G, int nvals, int stage, int flexible, hipStream_t s)
 {
-    HIP_TRY(h, launch_finalize(h->partials, G, nvals, h->sc, stage, flexible, s));
+    HIP_TRY(h, launch_finalize(h->partials, G, nvals, h->sc, stage, flexible, h->partials + 2 * (size_t)kMaxPartials,
+                               s));
     return TPMG_OK;
 }
 

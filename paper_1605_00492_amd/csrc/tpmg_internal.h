@@ -56,6 +56,9 @@ enum FinalizeStage : int {
 
 // Upper bound on per-dot partial sums (one per workgroup) in any reduction.
 constexpr int kMaxPartials = 1 << 19;
+// Segments of the first reduction stage when a dot has many partials; the
+// stage buffer holds 2 * kReduceSegs doubles.
+constexpr int kReduceSegs = 512;
 
 // ---- launchers (kernels.hip) --------------------------------------------
 // Each returns the launch status.  Shapes are validated by the caller.
@@ -98,7 +101,7 @@ hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b
 hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
                            double *partials, int *nblocks_out, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage,
-                           int flexible, hipStream_t s);
+                           int flexible, double *stage_buf, hipStream_t s);
 hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x,
                                 double *g, hipStream_t s);
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);

@@ -24,6 +24,8 @@ namespace {
 
 constexpr int kXcds = 8;
 constexpr int kStreamThreads = 256;
+// Elementwise CG kernels: workgroups of 256 (1024 streamed slower on MI355X).
+constexpr int kCgThreads = 256;
 constexpr double kDblMax = 1.7976931348623157e308;
 
 // Workgroups are dispatched to the XCDs round-robin.  Renumber them so that
@@ -837,7 +839,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
 
 // x += alpha p; r -= alpha q; partial (r,r) and, when z_old is given, (r, z_old);
 // optionally r32 = fl32(r) for the FP32 V-cycle.
-__global__ __launch_bounds__(256) void k_pcg_update(size_t n, double *__restrict__ x,
+__global__ __launch_bounds__(kCgThreads) void k_pcg_update(size_t n, double *__restrict__ x,
                                                     const double *__restrict__ p, double *__restrict__ r,
                                                     const double *__restrict__ q, float *__restrict__ r32,
                                                     const double *__restrict__ zold,
@@ -847,7 +849,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(size_t n, double *__restrict
 {
     const double alpha = sc->alpha;
     double rr = 0, rz = 0;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+    for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads) {
         x[g] += alpha * p[g];
         const double rv = r[g] - alpha * q[g];
         r[g] = rv;
@@ -860,15 +862,30 @@ __global__ __launch_bounds__(256) void k_pcg_update(size_t n, double *__restrict
     block_partials<2>(v, partials, gridDim.x, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_dot(size_t n, const double *__restrict__ a,
-                                             const double *__restrict__ b, const float *__restrict__ b32,
-                                             double *__restrict__ partials)
+__global__ __launch_bounds__(kCgThreads) void k_dot(size_t n, const double *__restrict__ a,
+                                                    const double *__restrict__ b, const float *__restrict__ b32,
+                                                    double *__restrict__ partials)
 {
     double s = 0;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256)
+    for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads)
         s += a[g] * (b32 ? (double)b32[g] : b[g]);
     double v[1] = {s};
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+// First stage for many partials: workgroup (s, v) sums the contiguous segment
+// s of value v's G partials in a fixed order, so the single-workgroup
+// finalisation reads kReduceSegs values instead of G.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partials, int G,
+                                                         double *__restrict__ out)
+{
+    const int v = blockIdx.y, seg = blockIdx.x;
+    const int lo = (int)((long long)G * seg / kReduceSegs), hi = (int)((long long)G * (seg + 1) / kReduceSegs);
+    const double *pv = partials + (size_t)v * G;
+    double acc = 0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) acc += pv[i];
+    double vv[1] = {acc};
+    block_partials<1>(vv, out + (size_t)v * kReduceSegs, kReduceSegs, seg);
 }
 
 // Fixed-order sum of the partials and the scalar recurrences of CG.
@@ -975,9 +992,9 @@ __global__ __launch_bounds__(256) void k_probe_copy(const v4u *__restrict__ s, v
         __builtin_nontemporal_store(__builtin_nontemporal_load(s + g), d + g);
 }
 
-int grid_for(size_t n, int per_thread = 4)
+int grid_for(size_t n, int per_thread = 4, int block = 256)
 {
-    size_t g = (n + (size_t)256 * per_thread - 1) / ((size_t)256 * per_thread);
+    size_t g = (n + (size_t)block * per_thread - 1) / ((size_t)block * per_thread);
     if (g < 1) g = 1;
     if (g > (size_t)kMaxPartials) g = kMaxPartials;
     return (int)g;
@@ -1241,28 +1258,44 @@ hipError_t launch_residual(const Level<double> &L, const double *x, const double
     });
 }
 
+// Elements per thread of the elementwise CG kernels (TPMG_EPT overrides).
+// Measured on 1024^2 x 128: the x/r update streams fastest at one (1.23 vs
+// 1.38 ms at four), the dot, with less work per element, at four (0.28 vs
+// 0.41 ms at one).
+int cg_ept(int dflt)
+{
+    static const int e = env_int("TPMG_EPT");
+    return (e == 1 || e == 2 || e == 4 || e == 8) ? e : dflt;
+}
+
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q, float *r32,
                              const double *zold, const float *zold32, const Scalars *sc, double *partials,
                              int *nblocks_out, hipStream_t s)
 {
-    const int G = grid_for(n);
+    const int G = grid_for(n, cg_ept(1), kCgThreads);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(256), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials);
+    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kCgThreads), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32, double *partials,
                       int *nblocks_out, hipStream_t s)
 {
-    const int G = grid_for(n);
+    const int G = grid_for(n, cg_ept(4), kCgThreads);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_dot, dim3(G), dim3(256), 0, s, n, a, b, b32, partials);
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kCgThreads), 0, s, n, a, b, b32, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage, int flexible,
-                           hipStream_t s)
+                           double *stage_buf, hipStream_t s)
 {
+    if (nblocks > 8 * kReduceSegs) {
+        hipLaunchKernelGGL(k_reduce_partials, dim3(kReduceSegs, nvals), dim3(256), 0, s, partials, nblocks,
+                           stage_buf);
+        partials = stage_buf;
+        nblocks = kReduceSegs;
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, nblocks, nvals, sc, stage, flexible);
     return hipGetLastError();
 }
