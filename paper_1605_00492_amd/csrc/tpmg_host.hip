@@ -554,19 +554,14 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
     }
     hipError_t e;
     const int plane0 = desc->n * desc->n;
-    if ((e = launch_copy_coeffs(c_dev, layout, (double *)h->l64[0].c, plane0, nz, s)) != hipSuccess)
-        return bail(hip_fail(h, e, "copy coefficients"));
     if ((e = launch_fill((double *)h->bad, 0.0, 1, s)) != hipSuccess ||
-        (e = launch_check_coeffs((const double *)h->l64[0].c, plane0, nz, h->bad, s)) != hipSuccess)
-        return bail(hip_fail(h, e, "check coefficients"));
+        (e = launch_copy_coeffs(c_dev, layout, (double *)h->l64[0].c, h->mixed ? (float *)h->l32[0].c : nullptr,
+                                plane0, nz, h->bad, s)) != hipSuccess)
+        return bail(hip_fail(h, e, "copy coefficients"));
     for (int l = 0; l + 1 < h->L; ++l)
-        if ((e = launch_coarsen(level_view<double>(h, l), (double *)h->l64[l + 1].c, s)) != hipSuccess)
+        if ((e = launch_coarsen(level_view<double>(h, l), (double *)h->l64[l + 1].c,
+                                h->mixed ? (float *)h->l32[l + 1].c : nullptr, s)) != hipSuccess)
             return bail(hip_fail(h, e, "coarsen"));
-    if (h->mixed)
-        for (int l = 0; l < h->L; ++l)
-            if ((e = launch_cast((const double *)h->l64[l].c, (float *)h->l32[l].c,
-                                 3 * (size_t)h->l64[l].plane * nz, s)) != hipSuccess)
-                return bail(hip_fail(h, e, "cast coefficients"));
     int bad = 0;
     if ((e = hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)

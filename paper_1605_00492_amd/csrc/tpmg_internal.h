@@ -72,11 +72,13 @@ hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *b
 template <typename T>
 hipError_t launch_coarse_gemv(const T *ainv, int m, const T *b, T *x, hipStream_t s);
 
-hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, hipStream_t s);
+// Face means onto level l+1 (FP64, and FP32 when c_coarse32 is given).
+hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, float *c_coarse32, hipStream_t s);
 hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s);
-hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, int plane, int nz,
+// Caller's faces -> level-0 storage (FP64, and FP32 when dst32 is given),
+// counting real faces that are not positive and finite into *bad.
+hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, float *dst32, int plane, int nz, int *bad,
                               hipStream_t s);
-hipError_t launch_check_coeffs(const double *c, int plane, int nz, int *bad, hipStream_t s);
 hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
 // level-major <-> column-major cell transposes (elem = 4 or 8 bytes)

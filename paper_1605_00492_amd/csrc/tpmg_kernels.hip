@@ -625,7 +625,8 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(const T *__restrict__ ainv,
 // ---- setup kernels ---------------------------------------------------------
 
 // Level l+1 faces from level l: mean of the fine faces covering each coarse face.
-__global__ __launch_bounds__(256) void k_coarsen(Level<double> F, double *__restrict__ cc)
+__global__ __launch_bounds__(256) void k_coarsen(Level<double> F, double *__restrict__ cc,
+                                                 float *__restrict__ cc32)
 {
     const int n = F.n, nz = F.nz, nc = n >> 1, planec = nc * nc;
     const size_t total = (size_t)planec * nz;
@@ -637,9 +638,17 @@ __global__ __launch_bounds__(256) void k_coarsen(Level<double> F, double *__rest
     const double *cE = F.c, *cN = F.c + fs, *cU = F.c + 2 * fs;
     const size_t o = (size_t)k * F.plane;
     const int a = (2 * J) * n + 2 * I;  // child (2I, 2J)
-    cc[g] = 0.5 * (cE[o + a + 1] + cE[o + a + n + 1]);
-    cc[cs + g] = 0.5 * (cN[o + a + n] + cN[o + a + n + 1]);
-    cc[2 * cs + g] = 0.25 * (cU[o + a] + cU[o + a + 1] + cU[o + a + n] + cU[o + a + n + 1]);
+    const double e = 0.5 * (cE[o + a + 1] + cE[o + a + n + 1]);
+    const double nn = 0.5 * (cN[o + a + n] + cN[o + a + n + 1]);
+    const double u = 0.25 * (cU[o + a] + cU[o + a + 1] + cU[o + a + n] + cU[o + a + n + 1]);
+    cc[g] = e;
+    cc[cs + g] = nn;
+    cc[2 * cs + g] = u;
+    if (cc32) {
+        cc32[g] = (float)e;
+        cc32[cs + g] = (float)nn;
+        cc32[2 * cs + g] = (float)u;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_cast(const double *__restrict__ s, float *__restrict__ d,
@@ -649,34 +658,27 @@ __global__ __launch_bounds__(256) void k_cast(const double *__restrict__ s, floa
         d[g] = (float)s[g];
 }
 
-// Input faces (either layout) -> level-major copy with the top U slot zeroed.
+// Input faces (either layout) -> level-major copy with the top U slot zeroed,
+// an FP32 copy when dst32 is given, and the count of real faces whose value
+// is not positive and finite added to *bad.
 __global__ __launch_bounds__(256) void k_copy_coeffs(const double *__restrict__ src, int layout,
-                                                     double *__restrict__ dst, int plane, int nz)
-{
-    const size_t per = (size_t)plane * nz;
-    const size_t total = 3 * per;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
-        const int f = (int)(g / per);
-        const size_t r = g % per;
-        const int k = (int)(r / plane), col = (int)(r % plane);
-        double v = (layout == 0) ? src[g] : src[((size_t)col * nz + k) * 3 + f];
-        if (f == 2 && k == nz - 1) v = 0.0;
-        dst[g] = v;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_check_coeffs(const double *__restrict__ c, int plane, int nz,
-                                                      int *__restrict__ bad)
+                                                     double *__restrict__ dst, float *__restrict__ dst32,
+                                                     int plane, int nz, int *__restrict__ bad)
 {
     const size_t per = (size_t)plane * nz;
     const size_t total = 3 * per;
     int cnt = 0;
     for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
         const int f = (int)(g / per);
-        const int k = (int)((g % per) / plane);
-        if (f == 2 && k == nz - 1) continue;
-        const double v = c[g];
-        if (!(v > 0.0) || !(v <= kDblMax)) ++cnt;
+        const size_t r = g % per;
+        const int k = (int)(r / plane), col = (int)(r % plane);
+        double v = (layout == 0) ? src[g] : src[((size_t)col * nz + k) * 3 + f];
+        if (f == 2 && k == nz - 1)
+            v = 0.0;
+        else if (!(v > 0.0) || !(v <= kDblMax))
+            ++cnt;
+        dst[g] = v;
+        if (dst32) dst32[g] = (float)v;
     }
     if (cnt) atomicAdd(bad, cnt);
 }
@@ -1165,10 +1167,10 @@ template hipError_t launch_resid_restrict<float>(const Level<float> &, const flo
 template hipError_t launch_coarse_gemv<double>(const double *, int, const double *, double *, hipStream_t);
 template hipError_t launch_coarse_gemv<float>(const float *, int, const float *, float *, hipStream_t);
 
-hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, hipStream_t s)
+hipError_t launch_coarsen(const Level<double> &F, double *c_coarse, float *c_coarse32, hipStream_t s)
 {
     const size_t total = (size_t)(F.n / 2) * (F.n / 2) * F.nz;
-    hipLaunchKernelGGL(k_coarsen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F, c_coarse);
+    hipLaunchKernelGGL(k_coarsen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F, c_coarse, c_coarse32);
     return hipGetLastError();
 }
 
@@ -1178,17 +1180,11 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, int plane, int nz, hipStream_t s)
+hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, float *dst32, int plane, int nz, int *bad,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy_coeffs, dim3(grid_for(3 * (size_t)plane * nz)), dim3(256), 0, s, src, layout,
-                       dst, plane, nz);
-    return hipGetLastError();
-}
-
-hipError_t launch_check_coeffs(const double *c, int plane, int nz, int *bad, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_check_coeffs, dim3(grid_for(3 * (size_t)plane * nz)), dim3(256), 0, s, c, plane, nz,
-                       bad);
+    hipLaunchKernelGGL(k_copy_coeffs, dim3(grid_for(3 * (size_t)plane * nz, 1)), dim3(256), 0, s, src, layout, dst,
+                       dst32, plane, nz, bad);
     return hipGetLastError();
 }
 
