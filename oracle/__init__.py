@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "tpmg_oracle.c"), os.path.join(_HERE, "oracle_level.inc")]
+_SRC = [os.path.join(_HERE, "tpmg_oracle.c"), os.path.join(_HERE, "oracle_level.inc"),
+        os.path.join(_HERE, "oracle_mixed.inc")]
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +62,10 @@ def lib():
                                  vp, _dp]
         L.oracle_pcg.restype = C.c_int
         L.oracle_face_gradient.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_mixed_apply.argtypes = [vp, _dp, _dp]
+        L.oracle_mixed_precondition.argtypes = [vp, C.c_int, _dp, _dp]
+        L.oracle_mixed_fgmres.argtypes = [vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int, vp, _dp]
+        L.oracle_mixed_fgmres.restype = C.c_int
         _lib = L
     return _lib
 
@@ -203,6 +208,41 @@ class Problem:
         g = [np.empty_like(lc) for _ in range(3)]
         lib().oracle_face_gradient(self._h, lc, xc, *g)
         return np.stack([from_columns(o, n, self.nz) for o in g])
+
+    # -- velocity-pressure system (faces E, N, U then pressure, stacked (4, nz, n, n)) --
+    def _mixed_cols(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        assert x.shape == (4, self.nz, self.n, self.n), x.shape
+        return np.ascontiguousarray(np.concatenate([to_columns(x[f]) for f in range(4)]))
+
+    def _mixed_logical(self, v):
+        m = self.n * self.n * self.nz
+        return np.stack([from_columns(v[f * m:(f + 1) * m], self.n, self.nz) for f in range(4)])
+
+    def mixed_apply(self, x):
+        xc = self._mixed_cols(x)
+        y = np.empty_like(xc)
+        lib().oracle_mixed_apply(self._h, xc, y)
+        return self._mixed_logical(y)
+
+    def mixed_precondition(self, r, fp32=False):
+        rc = self._mixed_cols(r)
+        z = np.empty_like(rc)
+        lib().oracle_mixed_precondition(self._h, 1 if fp32 else 0, rc, z)
+        return self._mixed_logical(z)
+
+    def mixed_fgmres(self, b, rtol=1e-5, restart=30, maxit=300, fp32=False):
+        """Returns (x, info) with info = dict(status, iterations, converged,
+        rel_residual (Arnoldi estimate), true_rel_residual, history)."""
+        bc = self._mixed_cols(b)
+        x = np.empty_like(bc)
+        hist = np.zeros(maxit + 1)
+        info = np.zeros(3)
+        st = lib().oracle_mixed_fgmres(self._h, bc, x, float(rtol), int(restart), int(maxit), 1 if fp32 else 0,
+                                       hist.ctypes.data_as(C.c_void_p), info)
+        it = int(info[2])
+        return self._mixed_logical(x), dict(status=st, iterations=it, converged=st >= 0, rel_residual=info[0],
+                                            true_rel_residual=info[1], history=hist[: it + 1].copy())
 
 
 def problem_for(w, c=None, **overrides) -> Problem:

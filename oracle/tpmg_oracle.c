@@ -21,7 +21,9 @@
  *   - the V-cycle (Sec. 3, two-grid cycle applied recursively);
  *   - an outer preconditioned CG on H (standard or flexible beta), with the
  *     V-cycle in double or in float;
- *   - the adjoint face gradient dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q).
+ *   - the adjoint face gradient dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q);
+ *   - the velocity-pressure system around it, its Schur-complement
+ *     preconditioner and the outer flexible GMRES (oracle_mixed.inc).
  *
  * Dot products accumulate in long double.
  */
@@ -366,3 +368,5 @@ void oracle_face_gradient(const oracle_problem *P, const double *lam, const doub
                 }
             }
 }
+
+#include "oracle_mixed.inc"

@@ -37,6 +37,7 @@ STREAM_RHS = 2        # right-hand side b
 STREAM_TARGET = 3     # target field x_t of the adjoint loss
 STREAM_FD_FACES = 4   # faces picked for finite-difference checks
 STREAM_TEST = 5       # test vectors
+STREAM_MIXED_RHS = 6  # right-hand side of the velocity-pressure system
 
 _CHUNK = 1 << 22
 
@@ -147,6 +148,15 @@ class Workload:
 
     def rhs(self, seed: int = SEED) -> np.ndarray:
         return normal(seed, STREAM_RHS, self.dof).reshape(self.nz, self.n, self.n)
+
+    def mixed_rhs(self, seed: int = SEED) -> np.ndarray:
+        """Right-hand side of the velocity-pressure system, (4, nz, n, n): the
+        E, N, U face components then the pressure; logical index
+        (f * nz + k) * n^2 + j * n + i.  The U slot of the top cell holds no
+        face and is 0."""
+        b = normal(seed, STREAM_MIXED_RHS, 4 * self.dof).reshape(4, self.nz, self.n, self.n)
+        b[2, self.nz - 1] = 0.0
+        return b
 
     def target(self, seed: int = SEED) -> np.ndarray:
         return normal(seed, STREAM_TARGET, self.dof).reshape(self.nz, self.n, self.n)
