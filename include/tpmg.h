@@ -223,6 +223,54 @@ tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t byte
 /* Release the handle (not the workspace).  NULL is accepted. */
 tpmg_status tpmg_destroy(tpmg_hierarchy *h);
 
+/*
+ * Velocity-pressure system around the pressure solve (Sec. 4.2,
+ * Eq. PressureVelocitySystem with buoyancy eliminated), on the finest level,
+ * FP64, level-major only.  A mixed vector holds four blocks of n*n*nz values,
+ * [uE | uN | uU | p]: the normal velocity on the E, N and U face slots of each
+ * cell (slot layout as the face coefficients; the U slot of the top cell
+ * holds no face and must be 0 on input, and is 0 on output) and the pressure.
+ * With the face weights w_f of the pressure operator (H = M3 + D W D^T):
+ *   A (u, p) = (M u - D^T p, D u + M3 p),
+ *   (D u)_p = outgoing minus incoming face values of cell p, (D^T x)_f = x_p - x_q,
+ *   (M u)_f = u_f / w_f + 1/4 sum u_f' / sqrt(w_f w_f') over the same-direction
+ *             faces f' that share a cell with f (a normalised lowest-order
+ *             Raviart-Thomas mass whose diagonal is 1/w_f, so that its diagonal
+ *             lumping (Eq. LumpedMass) gives exactly H).
+ * Requires n >= 2 (TPMG_ERR_SHAPE).  These calls use the hierarchy's internal
+ * vectors: they must not overlap other calls on the same handle.
+ *
+ * tpmg_mixed_apply: y = A x (asynchronous; x, y must not alias).
+ * tpmg_mixed_precondition: z = P^{-1} r, the Schur-complement factorisation
+ *   (Eq. SchurComplement) with the lumped inverse mass W for M^{-1} and one
+ *   V-cycle for H^{-1} (FP32 V-cycle on fl32 when fp32 = 1, mixed hierarchies
+ *   only): t = r_p - D W r_u, z_p = V t, z_u = W (r_u + D^T z_p).  Asynchronous.
+ * tpmg_mixed_solve: restarted flexible GMRES (right preconditioning with
+ *   P^{-1}, the V-cycle in the hierarchy's precision; Sec. 5 uses GMRES(30))
+ *   from x = 0 until the Arnoldi residual estimate is <= rtol ||b||.
+ *   Orthogonalisation: classical Gram-Schmidt applied twice, fixed-order
+ *   reductions.  workspace: caller-owned device memory of at least
+ *   tpmg_mixed_workspace_bytes(restart) bytes, 256-byte aligned
+ *   (TPMG_ERR_WORKSPACE otherwise).  info->rel_residual is the final estimate,
+ *   info->true_rel_residual = ||b - A x|| / ||b|| recomputed.  Returns TPMG_OK,
+ *   TPMG_NOT_CONVERGED (x holds the last iterate), TPMG_ERR_BREAKDOWN or an
+ *   argument/device error.  Synchronises `stream`.
+ */
+#define TPMG_MAX_RESTART 256
+typedef struct {
+    double rtol;      /* relative tolerance on ||b - A x|| / ||b||               */
+    int32_t restart;  /* Krylov vectors per cycle, 1..TPMG_MAX_RESTART           */
+    int32_t maxit;    /* total iterations (applications of A)                    */
+    double *history;  /* host [maxit + 1] residual estimates / ||b||, or NULL    */
+} tpmg_mixed_opts;
+tpmg_status tpmg_mixed_workspace_bytes(const tpmg_hierarchy *h, int32_t restart, size_t *bytes);
+tpmg_status tpmg_mixed_apply(const tpmg_hierarchy *h, const double *x_dev, double *y_dev, void *stream);
+tpmg_status tpmg_mixed_precondition(const tpmg_hierarchy *h, int32_t fp32, const double *r_dev, double *z_dev,
+                                    void *stream);
+tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *h, const double *b_dev, double *x_dev, void *workspace_dev,
+                             size_t workspace_bytes, const tpmg_mixed_opts *opts, tpmg_solve_info *info,
+                             void *stream);
+
 const char *tpmg_status_string(tpmg_status s);
 /* Last error text of a handle, or of the calling thread when h is NULL. */
 const char *tpmg_last_error(const tpmg_hierarchy *h);

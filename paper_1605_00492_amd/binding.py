@@ -23,7 +23,8 @@ K_SWEEP, K_SWEEP0, K_PROLSWEEP, K_RESTRICT, K_PCG_APPLY, K_PCG_UPDATE, K_VCYCLE 
 EXPORTS = [
     "tpmg_workspace_bytes", "tpmg_setup_hierarchy", "tpmg_level_n", "tpmg_apply_operator",
     "tpmg_vcycle", "tpmg_solve", "tpmg_face_gradient", "tpmg_smooth", "tpmg_residual_restrict",
-    "tpmg_prolong_smooth", "tpmg_coarse_solve", "tpmg_level_coefficients", "tpmg_profile_enable",
+    "tpmg_prolong_smooth", "tpmg_coarse_solve", "tpmg_mixed_workspace_bytes", "tpmg_mixed_apply",
+    "tpmg_mixed_precondition", "tpmg_mixed_solve", "tpmg_level_coefficients", "tpmg_profile_enable",
     "tpmg_profile_read", "tpmg_bandwidth_probe", "tpmg_destroy", "tpmg_status_string",
     "tpmg_last_error",
 ]
@@ -33,6 +34,10 @@ class TpmgError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status} ({detail})")
         self.status = status
+
+
+class MixedOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("history", C.c_void_p)]
 
 
 class Desc(C.Structure):
@@ -77,6 +82,10 @@ def lib():
         L.tpmg_residual_restrict.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.tpmg_prolong_smooth.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.tpmg_coarse_solve.argtypes = [vp, i32, vp, vp, vp]
+        L.tpmg_mixed_workspace_bytes.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
+        L.tpmg_mixed_apply.argtypes = [vp, vp, vp, vp]
+        L.tpmg_mixed_precondition.argtypes = [vp, i32, vp, vp, vp]
+        L.tpmg_mixed_solve.argtypes = [vp, vp, vp, vp, C.c_size_t, C.POINTER(MixedOpts), C.POINTER(SolveInfo), vp]
         L.tpmg_level_coefficients.argtypes = [vp, i32, i32, vp, vp]
         L.tpmg_profile_enable.argtypes = [vp, i32]
         L.tpmg_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -300,6 +309,62 @@ class Hierarchy:
         _check(lib().tpmg_level_coefficients(self.handle, level, int(fp32), _ptr(out), _stream(self.device)),
                "tpmg_level_coefficients", self.handle)
         return out
+
+    # -- velocity-pressure system (finest level, FP64, level-major) -------------------
+    def _mixed_vec(self, t: torch.Tensor, name: str):
+        shape = (4, self.nz, self.n, self.n)
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and tuple(t.shape) == shape):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+        if self.layout != LEVEL_MAJOR:
+            raise ValueError("the velocity-pressure system is level-major only")
+        return t
+
+    def mixed_apply(self, x: torch.Tensor) -> torch.Tensor:
+        """y = A x for x = [u_E, u_N, u_U, p] stacked as (4, nz, n, n)."""
+        self._mixed_vec(x, "x")
+        y = torch.empty_like(x)
+        _check(lib().tpmg_mixed_apply(self.handle, _ptr(x), _ptr(y), _stream(self.device)), "tpmg_mixed_apply",
+               self.handle)
+        return y
+
+    def mixed_precondition(self, r: torch.Tensor, fp32: bool | None = None) -> torch.Tensor:
+        """z = P^{-1} r (Schur-complement factorisation, one V-cycle)."""
+        self._mixed_vec(r, "r")
+        z = torch.empty_like(r)
+        f32 = self.mixed if fp32 is None else bool(fp32)
+        _check(lib().tpmg_mixed_precondition(self.handle, int(f32), _ptr(r), _ptr(z), _stream(self.device)),
+               "tpmg_mixed_precondition", self.handle)
+        return z
+
+    def mixed_workspace_bytes(self, restart: int = 30) -> int:
+        nb = C.c_size_t(0)
+        _check(lib().tpmg_mixed_workspace_bytes(self.handle, int(restart), C.byref(nb)),
+               "tpmg_mixed_workspace_bytes", self.handle)
+        return nb.value
+
+    def mixed_solve(self, b: torch.Tensor, rtol: float = 1e-5, restart: int = 30, maxit: int = 300,
+                    history: bool = False, workspace: torch.Tensor | None = None):
+        """Restarted flexible GMRES on A x = b with the Schur-complement
+        preconditioner.  Returns (x, info dict)."""
+        import numpy as np
+        self._mixed_vec(b, "b")
+        x = torch.empty_like(b)
+        need = self.mixed_workspace_bytes(restart)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        opts = MixedOpts()
+        opts.rtol, opts.restart, opts.maxit = float(rtol), int(restart), int(maxit)
+        hist = np.zeros(maxit + 1) if history else None
+        opts.history = hist.ctypes.data_as(C.c_void_p) if hist is not None else None
+        info = SolveInfo()
+        st = lib().tpmg_mixed_solve(self.handle, _ptr(b), _ptr(x), _ptr(workspace), need, C.byref(opts),
+                                    C.byref(info), _stream(self.device))
+        _check(st, "tpmg_mixed_solve", self.handle, ok=(OK, NOT_CONVERGED))
+        res = dict(iterations=info.iterations, converged=bool(info.converged), rel_residual=info.rel_residual,
+                   true_rel_residual=info.true_rel_residual, status=st)
+        if hist is not None:
+            res["history"] = hist[: info.iterations + 1].copy()
+        return x, res
 
     # -- profiling ------------------------------------------------------------------
     def profile_enable(self, on: bool = True):

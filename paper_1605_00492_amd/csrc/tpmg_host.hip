@@ -53,7 +53,8 @@ struct tpmg_hierarchy {
     double *partials = nullptr;
     Scalars *sc = nullptr;
     int *bad = nullptr;
-    Scalars *sc_host = nullptr;  // pinned
+    Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax doubles (dots_host)
+    double *dots_host = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     std::string err;
@@ -509,8 +510,10 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
         delete h;
         return code;
     };
-    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + kMultiMax * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess)
         return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
+    h->dots_host = reinterpret_cast<double *>(reinterpret_cast<char *>(h->sc_host) + sizeof(Scalars));
 
     // per-level scalars: s_k, t_{k+1/2}
     const int nz = desc->nz;
@@ -916,6 +919,262 @@ tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t byte
     hipError_t e = launch_probe_copy(dst_dev, src_dev, bytes, as_stream(stream));
     if (e != hipSuccess) return hip_fail(nullptr, e, "probe copy");
     return TPMG_OK;
+}
+
+// ---- velocity-pressure system (Sec. 4.2, Eq. PressureVelocitySystem; Sec. 5) ----
+
+namespace {
+
+struct MixedWs {
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *partials = nullptr, *stage = nullptr, *out = nullptr;
+    size_t M = 0;
+};
+
+// Carve the GMRES workspace: V (restart + 1 vectors), Z (restart), w, partial
+// sums, reduction stage and results.  With base == nullptr only the size.
+size_t plan_mixed(const tpmg_hierarchy *h, int restart, char *base, MixedWs *W)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> double * {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t M = 4 * h->ncell;
+    W->M = M;
+    W->V = take((size_t)(restart + 1) * M * sizeof(double));
+    W->Z = take((size_t)restart * M * sizeof(double));
+    W->w = take(M * sizeof(double));
+    W->partials = take((size_t)kMultiMax * kMaxPartials * sizeof(double));
+    W->stage = take((size_t)kMultiMax * kReduceSegs * sizeof(double));
+    W->out = take((size_t)kMultiMax * sizeof(double));
+    return (off + kAlign - 1) / kAlign * kAlign;
+}
+
+// z = P^{-1} r: t = r_p - D W r_u, z_p = V t (hierarchy precision), z_u = W (r_u + D^T z_p).
+tpmg_status mixed_precondition(tpmg_hierarchy *h, const double *r, double *z, bool fp32, hipStream_t s)
+{
+    const Level<double> L0 = level_view<double>(h, 0);
+    HIP_TRY(h, launch_mixed_pre1(L0, r, h->r, fp32 ? h->r32 : nullptr, s));
+    tpmg_status st = fp32 ? vcycle<float>(h, h->r32, h->z32, s) : vcycle<double>(h, h->r, h->z, s);
+    if (st != TPMG_OK) return st;
+    HIP_TRY(h, launch_mixed_pre2(L0, r, fp32 ? nullptr : h->z, fp32 ? h->z32 : nullptr, z, s));
+    return TPMG_OK;
+}
+
+// res[i] = (w, v_i), i < nv, in groups of kMultiMax; synchronises.
+tpmg_status mixed_dots(tpmg_hierarchy *h, const MixedWs &W, const double *w, const double *const *v, int nv,
+                       double *res, hipStream_t s)
+{
+    for (int i0 = 0; i0 < nv; i0 += kMultiMax) {
+        const int g = std::min(kMultiMax, nv - i0);
+        HIP_TRY(h, launch_multidot(W.M, w, v + i0, g, W.partials, W.stage, W.out, s));
+        HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, g * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        for (int i = 0; i < g; ++i) res[i0 + i] = h->dots_host[i];
+    }
+    return TPMG_OK;
+}
+
+// y += sum a_i v_i in groups; with norm2 != nullptr also returns (y, y).
+tpmg_status mixed_axpys(tpmg_hierarchy *h, const MixedWs &W, double *y, const double *const *v, const double *a,
+                        int nv, double *norm2, hipStream_t s)
+{
+    int G = 0;
+    for (int i0 = 0; i0 < nv; i0 += kMultiMax) {
+        const int g = std::min(kMultiMax, nv - i0);
+        const bool last = i0 + g >= nv;
+        HIP_TRY(h, launch_multiaxpy(W.M, y, v + i0, a + i0, g, (last && norm2) ? W.partials : nullptr, &G, s));
+    }
+    if (norm2) {
+        HIP_TRY(h, launch_sum_partials(W.partials, G, 1, W.stage, W.out, s));
+        HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        *norm2 = h->dots_host[0];
+    }
+    return TPMG_OK;
+}
+
+tpmg_status check_mixed_level(tpmg_hierarchy *h)
+{
+    if (h->l64[0].n < 2) return fail(h, TPMG_ERR_SHAPE, "the velocity-pressure system needs n >= 2");
+    return TPMG_OK;
+}
+
+}  // namespace
+
+tpmg_status tpmg_mixed_workspace_bytes(const tpmg_hierarchy *h, int32_t restart, size_t *bytes)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    if (!bytes) return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "bytes is NULL");
+    if (restart < 1 || restart > TPMG_MAX_RESTART)
+        return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "restart out of range");
+    MixedWs W;
+    *bytes = plan_mixed(h, restart, nullptr, &W);
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_mixed_apply(const tpmg_hierarchy *hc, const double *x_dev, double *y_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(hc)) != TPMG_OK) return st;
+    tpmg_hierarchy *h = const_cast<tpmg_hierarchy *>(hc);
+    if ((st = check_ptrs(h, {x_dev, y_dev})) != TPMG_OK || (st = check_mixed_level(h)) != TPMG_OK) return st;
+    if ((const void *)x_dev == (const void *)y_dev) return fail(h, TPMG_ERR_INVALID_ARG, "x and y must not alias");
+    HIP_TRY(h, launch_mixed_apply(level_view<double>(h, 0), x_dev, y_dev, as_stream(stream)));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_mixed_precondition(const tpmg_hierarchy *hc, int32_t fp32, const double *r_dev, double *z_dev,
+                                    void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(hc)) != TPMG_OK) return st;
+    tpmg_hierarchy *h = const_cast<tpmg_hierarchy *>(hc);
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {r_dev, z_dev})) != TPMG_OK ||
+        (st = check_mixed_level(h)) != TPMG_OK)
+        return st;
+    if ((const void *)r_dev == (const void *)z_dev) return fail(h, TPMG_ERR_INVALID_ARG, "r and z must not alias");
+    return mixed_precondition(h, r_dev, z_dev, fp32 == 1, as_stream(stream));
+}
+
+tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_dev, void *workspace_dev,
+                             size_t workspace_bytes, const tpmg_mixed_opts *opts, tpmg_solve_info *info, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(hc)) != TPMG_OK) return st;
+    tpmg_hierarchy *h = const_cast<tpmg_hierarchy *>(hc);
+    if ((st = check_ptrs(h, {b_dev, x_dev})) != TPMG_OK || (st = check_mixed_level(h)) != TPMG_OK) return st;
+    if (!opts) return fail(h, TPMG_ERR_INVALID_ARG, "opts is NULL");
+    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || opts->restart < 1 || opts->restart > TPMG_MAX_RESTART)
+        return fail(h, TPMG_ERR_INVALID_ARG, "bad mixed-solve options");
+    if ((const void *)b_dev == (const void *)x_dev) return fail(h, TPMG_ERR_INVALID_ARG, "b and x must not alias");
+    const int R = opts->restart;
+    MixedWs W;
+    const size_t need = plan_mixed(h, R, nullptr, &W);
+    if (!workspace_dev || workspace_bytes < need || ((uintptr_t)workspace_dev % kAlign) != 0)
+        return fail(h, TPMG_ERR_WORKSPACE, "mixed workspace missing, misaligned or smaller than tpmg_mixed_workspace_bytes");
+    plan_mixed(h, R, static_cast<char *>(workspace_dev), &W);
+    hipStream_t s = as_stream(stream);
+    const size_t M = W.M;
+    const Level<double> L0 = level_view<double>(h, 0);
+    const bool fp32 = h->mixed;
+    double *x = x_dev;
+    const double *b = b_dev;
+
+    HIP_TRY(h, launch_fill(x, 0.0, M, s));
+    HIP_TRY(h, launch_copy(W.w, b, M, s));
+    double bb = 0.0;
+    if ((st = mixed_dots(h, W, b, &b, 1, &bb, s)) != TPMG_OK) return st;
+    const double bnorm = std::sqrt(bb);
+    if (opts->history) opts->history[0] = bnorm > 0.0 ? 1.0 : 0.0;
+    std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), c(R + 1);
+    std::vector<const double *> vptr(R + 1), zptr(R);
+    std::vector<double> coef(R + 1);
+    for (int i = 0; i <= R; ++i) vptr[i] = W.V + (size_t)i * M;
+    for (int i = 0; i < R; ++i) zptr[i] = W.Z + (size_t)i * M;
+    int it = 0;
+    bool converged = false;
+    double est = bnorm > 0.0 ? 1.0 : 0.0;
+    tpmg_status result = TPMG_NOT_CONVERGED;
+    if (!std::isfinite(bnorm)) {
+        result = fail(h, TPMG_ERR_BREAKDOWN, "non-finite right-hand side");
+    } else if (bnorm == 0.0) {
+        converged = true;
+        est = 0.0;
+    }
+    while (!converged && result == TPMG_NOT_CONVERGED && it < opts->maxit) {
+        double rr = 0.0;
+        const double *wp = W.w;
+        if ((st = mixed_dots(h, W, W.w, &wp, 1, &rr, s)) != TPMG_OK) return st;
+        const double beta = std::sqrt(rr);
+        if (beta <= opts->rtol * bnorm) {
+            converged = true;
+            est = beta / bnorm;
+            break;
+        }
+        HIP_TRY(h, launch_axpby(M, 1.0 / beta, W.w, 0.0, nullptr, W.V, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jj = 0;
+        bool conv = false;
+        for (int j = 0; j < R && it < opts->maxit; ++j) {
+            double *zj = W.Z + (size_t)j * M;
+            if ((st = mixed_precondition(h, vptr[j], zj, fp32, s)) != TPMG_OK) return st;
+            HIP_TRY(h, launch_mixed_apply(L0, zj, W.w, s));
+            // classical Gram-Schmidt, applied twice
+            std::fill(hcol.begin(), hcol.end(), 0.0);
+            double hn2 = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((st = mixed_dots(h, W, W.w, vptr.data(), j + 1, c.data(), s)) != TPMG_OK) return st;
+                for (int i = 0; i <= j; ++i) {
+                    hcol[i] += c[i];
+                    coef[i] = -c[i];
+                }
+                if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, pass == 1 ? &hn2 : nullptr, s)) !=
+                    TPMG_OK)
+                    return st;
+            }
+            const double hn = std::sqrt(hn2);
+            if (!std::isfinite(hn)) {
+                result = fail(h, TPMG_ERR_BREAKDOWN, "non-finite Arnoldi vector");
+                break;
+            }
+            for (int i = 0; i <= j; ++i) H[(size_t)i * R + j] = hcol[i];
+            H[(size_t)(j + 1) * R + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * R + j], cc = H[(size_t)(i + 1) * R + j];
+                H[(size_t)i * R + j] = cs[i] * a + sn[i] * cc;
+                H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * cc;
+            }
+            const double a = H[(size_t)j * R + j], cc = H[(size_t)(j + 1) * R + j];
+            const double den = std::hypot(a, cc);
+            cs[j] = a / den;
+            sn[j] = cc / den;
+            H[(size_t)j * R + j] = den;
+            H[(size_t)(j + 1) * R + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            est = std::fabs(g[j + 1]) / bnorm;
+            if (opts->history) opts->history[it] = est;
+            jj = j + 1;
+            if (std::fabs(g[j + 1]) <= opts->rtol * bnorm || hn == 0.0) {
+                conv = true;
+                break;
+            }
+            HIP_TRY(h, launch_axpby(M, 1.0 / hn, W.w, 0.0, nullptr, W.V + (size_t)(j + 1) * M, s));
+        }
+        if (result != TPMG_NOT_CONVERGED) break;
+        for (int i = jj - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < jj; ++l) t -= H[(size_t)i * R + l] * y[l];
+            y[i] = t / H[(size_t)i * R + i];
+        }
+        if (jj > 0 && (st = mixed_axpys(h, W, x, zptr.data(), y.data(), jj, nullptr, s)) != TPMG_OK) return st;
+        if (conv) {
+            converged = true;
+            break;
+        }
+        HIP_TRY(h, launch_mixed_apply(L0, x, W.w, s));
+        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, W.w, W.w, s));
+    }
+    if (converged) result = TPMG_OK;
+    if (info) {
+        HIP_TRY(h, launch_mixed_apply(L0, x, W.w, s));
+        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, W.w, W.w, s));
+        double tt = 0.0;
+        const double *wp = W.w;
+        if ((st = mixed_dots(h, W, W.w, &wp, 1, &tt, s)) != TPMG_OK) return st;
+        info->iterations = it;
+        info->converged = converged ? 1 : 0;
+        info->rel_residual = est;
+        info->true_rel_residual = bnorm > 0.0 ? std::sqrt(tt) / bnorm : 0.0;
+    }
+    HIP_TRY(h, hipStreamSynchronize(s));
+    return result;
 }
 
 tpmg_status tpmg_destroy(tpmg_hierarchy *h)

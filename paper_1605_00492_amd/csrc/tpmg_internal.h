@@ -108,6 +108,26 @@ hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const
                                 double *g, hipStream_t s);
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// ---- velocity-pressure system (mixed.hip), finest level, FP64 ----------------
+// Vectors of the outer GMRES combined per kernel launch.
+constexpr int kMultiMax = 8;
+hipError_t launch_mixed_apply(const Level<double> &L, const double *x, double *y, hipStream_t s);
+// t = r_p - D W r_u (and fl32(t) into t32 when given)
+hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double *t, float *t32, hipStream_t s);
+// z_u = W (r_u + D^T y), z_p = y, y from y64 or y32
+hipError_t launch_mixed_pre2(const Level<double> &L, const double *r, const double *y64, const float *y32, double *z,
+                             hipStream_t s);
+// out[i] = (w, v_i), i < nv <= kMultiMax, fixed-order reductions
+hipError_t launch_multidot(size_t n, const double *w, const double *const *v, int nv, double *partials,
+                           double *stage, double *out, hipStream_t s);
+// y += sum a_i v_i; norm_partials (optional) receives the partial sums of (y, y)
+hipError_t launch_multiaxpy(size_t n, double *y, const double *const *v, const double *a, int nv,
+                            double *norm_partials, int *nblocks_out, hipStream_t s);
+// y = a x + b z (z == nullptr: y = a x); y may alias z
+hipError_t launch_axpby(size_t n, double a, const double *x, double b, const double *z, double *y, hipStream_t s);
+// out[v] = fixed-order sum of the G partials of value v (v < nvals <= kMultiMax)
+hipError_t launch_sum_partials(const double *partials, int G, int nvals, double *stage, double *out, hipStream_t s);
+
 // Sweep chunking for a precision and column height: M cells per chunk, CPW
 // chunks per wavefront, P wavefronts per 64-column tile; false if nz is not
 // supported.
