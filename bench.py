@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # Compulsory HBM bytes per finest-level DOF (words x 4 bytes for the FP32 V-cycle):
 SWEEP_WORDS = 6            # reads u, b, c_E, c_N, c_U; writes u'
 VCYCLE_WORDS = 28.5 * 4 / 3  # 28.5 words on the finest level, times sum 4^-l
-KERNEL_SOURCES = ["paper_1605_00492_amd/csrc/tpmg_kernels.hip"]
+KERNEL_SOURCES = ["paper_1605_00492_amd/csrc/tpmg_kernels.hip", "paper_1605_00492_amd/csrc/tpmg_device.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_1024x1024x128_counters.json")
 
 
@@ -205,6 +205,47 @@ def robustness(tp, torch, w, dev, args):
     print(json.dumps(out), flush=True)
 
 
+def mixed_system(tp, torch, w, dev, args):
+    """The velocity-pressure system around the pressure solve (Sec. 4.2,
+    Sec. 5.1): restarted flexible GMRES to rtol 1e-5 with the Schur-complement
+    preconditioner, the pressure block approximated by one multigrid V-cycle
+    (FP64 or FP32) or by the single-level method, at nu_CFL = 2 (a_h = 1, the
+    workload) and nu_CFL = 8 (a_h = 16, the paper's runs).  GMRES(30) on
+    512^2 x 64 and GMRES(20) on the full grid (memory: 2 (m + 1) mixed vectors)."""
+    import numpy as np
+
+    import synthetic as syn
+    out = {"rtol": 1e-5, "runs": []}
+    for n, nz, restart in ((512, 64, 30), (w.n, w.nz, 20)):
+        ww = syn.scaled(w, n, nz=nz, levels=int(round(np.log2(n // 16))) + 1, name=f"{w.name}@{n}x{n}x{nz}")
+        c = torch.from_numpy(ww.coefficients()).to(dev)
+        b = torch.from_numpy(ww.mixed_rhs()).to(dev)
+        for a_h in (1.0, 16.0):
+            for name, kw in (("mg_fp32", dict(levels=ww.levels, precision="mixed")),
+                             ("mg_fp64", dict(levels=ww.levels, precision="fp64")),
+                             ("single_level", dict(levels=1, precision="mixed"))):
+                H = tp.Hierarchy(c, dz=ww.dz(), a_h=a_h, a_z=ww.a_z, nu=ww.nu, omega=ww.omega, **kw)
+                ws = torch.empty(H.mixed_workspace_bytes(restart), dtype=torch.uint8, device=dev)
+                H.mixed_solve(b, rtol=1e-5, restart=restart, maxit=300, workspace=ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = H.mixed_solve(b, rtol=1e-5, restart=restart, maxit=300, workspace=ws)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                H.close()
+                del ws, x
+                torch.cuda.empty_cache()
+                row = dict(grid=[n, n, nz], unknowns=4 * ww.dof - n * n, a_h=a_h, nu_cfl=2.0 * a_h ** 0.5,
+                           preconditioner=name, restart=restart, iterations=info["iterations"],
+                           converged=info["converged"], true_rel_residual=info["true_rel_residual"], solve_ms=ms,
+                           ms_per_iteration=ms / max(info["iterations"], 1))
+                out["runs"].append(row)
+                log(f"mixed system {row}")
+        del c, b
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +253,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large_1024x1024x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-system", action="store_true",
+                    help="velocity-pressure system: GMRES with multigrid vs single-level preconditioners")
     ap.add_argument("--robustness", action="store_true",
                     help="Courant-number and resolution study (single level vs multigrid variants)")
     ap.add_argument("--probe", action="store_true",
@@ -233,6 +276,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.robustness:
         robustness(tp, torch, w, dev, args)
+        return
+    if args.mixed_system:
+        mixed_system(tp, torch, w, dev, args)
         return
     log(f"generating {w.name} ({w.dof} DOF)")
     c = torch.from_numpy(w.coefficients()).to(dev)

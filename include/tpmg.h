@@ -248,8 +248,8 @@ tpmg_status tpmg_destroy(tpmg_hierarchy *h);
  * tpmg_mixed_solve: restarted flexible GMRES (right preconditioning with
  *   P^{-1}, the V-cycle in the hierarchy's precision; Sec. 5 uses GMRES(30))
  *   from x = 0 until the Arnoldi residual estimate is <= rtol ||b||.
- *   Orthogonalisation: classical Gram-Schmidt applied twice, fixed-order
- *   reductions.  workspace: caller-owned device memory of at least
+ *   Orthogonalisation: classical Gram-Schmidt, repeated when the first pass
+ *   cancels more than a factor 1/sqrt(2) of the norm; fixed-order reductions.  workspace: caller-owned device memory of at least
  *   tpmg_mixed_workspace_bytes(restart) bytes, 256-byte aligned
  *   (TPMG_ERR_WORKSPACE otherwise).  info->rel_residual is the final estimate,
  *   info->true_rel_residual = ||b - A x|| / ||b|| recomputed.  Returns TPMG_OK,

@@ -53,7 +53,7 @@ struct tpmg_hierarchy {
     double *partials = nullptr;
     Scalars *sc = nullptr;
     int *bad = nullptr;
-    Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax doubles (dots_host)
+    Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax + 1 doubles (dots_host)
     double *dots_host = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -510,7 +510,7 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
         delete h;
         return code;
     };
-    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + kMultiMax * sizeof(double), hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + (kMultiMax + 1) * sizeof(double), hipHostMallocDefault) !=
         hipSuccess)
         return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
     h->dots_host = reinterpret_cast<double *>(reinterpret_cast<char *>(h->sc_host) + sizeof(Scalars));
@@ -946,9 +946,9 @@ size_t plan_mixed(const tpmg_hierarchy *h, int restart, char *base, MixedWs *W)
     W->V = take((size_t)(restart + 1) * M * sizeof(double));
     W->Z = take((size_t)restart * M * sizeof(double));
     W->w = take(M * sizeof(double));
-    W->partials = take((size_t)kMultiMax * kMaxPartials * sizeof(double));
-    W->stage = take((size_t)kMultiMax * kReduceSegs * sizeof(double));
-    W->out = take((size_t)kMultiMax * sizeof(double));
+    W->partials = take((size_t)(kMultiMax + 1) * kMaxPartials * sizeof(double));
+    W->stage = take((size_t)(kMultiMax + 1) * kReduceSegs * sizeof(double));
+    W->out = take((size_t)(kMultiMax + 1) * sizeof(double));
     return (off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -1071,7 +1071,7 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
     const double bnorm = std::sqrt(bb);
     if (opts->history) opts->history[0] = bnorm > 0.0 ? 1.0 : 0.0;
     std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), c(R + 1);
-    std::vector<const double *> vptr(R + 1), zptr(R);
+    std::vector<const double *> vptr(R + 2), zptr(R);
     std::vector<double> coef(R + 1);
     for (int i = 0; i <= R; ++i) vptr[i] = W.V + (size_t)i * M;
     for (int i = 0; i < R; ++i) zptr[i] = W.Z + (size_t)i * M;
@@ -1104,18 +1104,38 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
             double *zj = W.Z + (size_t)j * M;
             if ((st = mixed_precondition(h, vptr[j], zj, fp32, s)) != TPMG_OK) return st;
             HIP_TRY(h, launch_mixed_apply(L0, zj, W.w, s));
-            // classical Gram-Schmidt, applied twice
+            // classical Gram-Schmidt with selective reorthogonalisation: a
+            // second pass only when the first one cancels more than a factor
+            // 1/sqrt(2) of the norm of w (the "twice is enough" criterion)
             std::fill(hcol.begin(), hcol.end(), 0.0);
             double hn2 = 0.0;
-            for (int pass = 0; pass < 2; ++pass) {
-                if ((st = mixed_dots(h, W, W.w, vptr.data(), j + 1, c.data(), s)) != TPMG_OK) return st;
+            vptr[j + 1] = W.w;  // (w, w) rides along with the first-pass dots
+            if ((st = mixed_dots(h, W, W.w, vptr.data(), j + 2, c.data(), s)) != TPMG_OK) return st;
+            vptr[j + 1] = W.V + (size_t)(j + 1) * M;
+            const double ww = c[j + 1];
+            for (int i = 0; i <= j; ++i) {
+                hcol[i] = c[i];
+                coef[i] = -c[i];
+            }
+            if (j + 1 <= kMultiMax) {
+                // first update fused with the second pass's dots and the norm
+                HIP_TRY(h, launch_multiaxpy_dot(M, W.w, vptr.data(), coef.data(), j + 1, W.partials, W.stage, W.out,
+                                                s));
+                HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(h, hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) c[i] = h->dots_host[i];
+                hn2 = h->dots_host[j + 1];
+            } else if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) {
+                return st;
+            }
+            if (!(hn2 > 0.5 * ww)) {
+                if (j + 1 > kMultiMax && (st = mixed_dots(h, W, W.w, vptr.data(), j + 1, c.data(), s)) != TPMG_OK)
+                    return st;
                 for (int i = 0; i <= j; ++i) {
                     hcol[i] += c[i];
                     coef[i] = -c[i];
                 }
-                if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, pass == 1 ? &hn2 : nullptr, s)) !=
-                    TPMG_OK)
-                    return st;
+                if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) return st;
             }
             const double hn = std::sqrt(hn2);
             if (!std::isfinite(hn)) {

@@ -110,7 +110,7 @@ hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream
 
 // ---- velocity-pressure system (mixed.hip), finest level, FP64 ----------------
 // Vectors of the outer GMRES combined per kernel launch.
-constexpr int kMultiMax = 8;
+constexpr int kMultiMax = 16;
 hipError_t launch_mixed_apply(const Level<double> &L, const double *x, double *y, hipStream_t s);
 // t = r_p - D W r_u (and fl32(t) into t32 when given)
 hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double *t, float *t32, hipStream_t s);
@@ -123,6 +123,10 @@ hipError_t launch_multidot(size_t n, const double *w, const double *const *v, in
 // y += sum a_i v_i; norm_partials (optional) receives the partial sums of (y, y)
 hipError_t launch_multiaxpy(size_t n, double *y, const double *const *v, const double *a, int nv,
                             double *norm_partials, int *nblocks_out, hipStream_t s);
+// y += sum a_i v_i, then out[i] = (y, v_i) for i < nv and out[nv] = (y, y)
+// (nv + 1 values: partials, stage and out hold kMultiMax + 1 of them)
+hipError_t launch_multiaxpy_dot(size_t n, double *y, const double *const *v, const double *a, int nv,
+                                double *partials, double *stage, double *out, hipStream_t s);
 // y = a x + b z (z == nullptr: y = a x); y may alias z
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, const double *z, double *y, hipStream_t s);
 // out[v] = fixed-order sum of the G partials of value v (v < nvals <= kMultiMax)

@@ -15,6 +15,8 @@
 //   (D^T x)_f = x_p - x_q,
 //   A (u, p)  = (M u - D^T p, D u + M3 p).
 // All kernels stream: thread = (column, chunk of KC cells along k).
+#include <type_traits>
+
 #include "tpmg_device.h"
 
 namespace tpmg {
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_apply(Level<double> L,
         wUm = L.wz[k0 - 1] * cU[om];
         xUm = xU[om];
     }
-#pragma unroll 4
+#pragma unroll 2
     for (int t = 0; t < kMixedKC; ++t) {
         const int k = k0 + t;
         if (k >= nz) break;
@@ -201,6 +203,31 @@ __global__ __launch_bounds__(256) void k_multiaxpy(size_t n, double *__restrict_
     }
 }
 
+// y += sum_i a_i v_i, then the block parts of (y, v_i), i < NV, and (y, y):
+// the second Gram-Schmidt pass's dots ride on the first pass's update.
+template <int NV>
+__global__ __launch_bounds__(256) void k_multiaxpy_dot(size_t n, double *__restrict__ y, VecSet S,
+                                                       double *__restrict__ partials)
+{
+    double acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        double v[NV];
+        double s = y[g];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            v[i] = S.v[i][g];
+            s += S.a[i] * v[i];
+        }
+        y[g] = s;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += s * v[i];
+        acc[NV] += s * s;
+    }
+    block_partials<NV + 1>(acc, partials, gridDim.x, blockIdx.x);
+}
+
 // y = a x + b z (z may be null: y = a x).
 __global__ __launch_bounds__(256) void k_axpby(size_t n, double a, const double *__restrict__ x, double b,
                                                const double *__restrict__ z, double *__restrict__ y)
@@ -237,6 +264,25 @@ template <int NV>
 void launch_multiaxpy_n(size_t n, double *y, const VecSet &S, double *partials, int G, hipStream_t s)
 {
     hipLaunchKernelGGL((k_multiaxpy<NV>), dim3(G), dim3(256), 0, s, n, y, S, partials);
+}
+
+template <int NV>
+void launch_multiaxpy_dot_n(size_t n, double *y, const VecSet &S, double *partials, int G, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_multiaxpy_dot<NV>), dim3(G), dim3(256), 0, s, n, y, S, partials);
+}
+
+// Calls f(std::integral_constant<int, NV>) for 1 <= nv <= kMultiMax.
+template <int NV = 1, class F>
+void dispatch_nv(int nv, F &&f)
+{
+    if constexpr (NV < kMultiMax) {
+        if (nv > NV) {
+            dispatch_nv<NV + 1>(nv, f);
+            return;
+        }
+    }
+    f(std::integral_constant<int, NV>());
 }
 
 // Partials per dot of the vector kernels: about four elements per thread,
@@ -277,16 +323,7 @@ hipError_t launch_multidot(size_t n, const double *w, const double *const *v, in
     VecSet S{};
     for (int i = 0; i < nv; ++i) S.v[i] = v[i];
     const int G = vec_grid(n);
-    switch (nv) {
-    case 1: launch_multidot_n<1>(n, w, S, partials, G, s); break;
-    case 2: launch_multidot_n<2>(n, w, S, partials, G, s); break;
-    case 3: launch_multidot_n<3>(n, w, S, partials, G, s); break;
-    case 4: launch_multidot_n<4>(n, w, S, partials, G, s); break;
-    case 5: launch_multidot_n<5>(n, w, S, partials, G, s); break;
-    case 6: launch_multidot_n<6>(n, w, S, partials, G, s); break;
-    case 7: launch_multidot_n<7>(n, w, S, partials, G, s); break;
-    default: launch_multidot_n<8>(n, w, S, partials, G, s); break;
-    }
+    dispatch_nv(nv, [&](auto NVc) { launch_multidot_n<decltype(NVc)::value>(n, w, S, partials, G, s); });
     return launch_sum_partials(partials, G, nv, stage, out, s);
 }
 
@@ -301,17 +338,22 @@ hipError_t launch_multiaxpy(size_t n, double *y, const double *const *v, const d
     }
     const int G = vec_grid(n);
     if (nblocks_out) *nblocks_out = G;
-    switch (nv) {
-    case 1: launch_multiaxpy_n<1>(n, y, S, norm_partials, G, s); break;
-    case 2: launch_multiaxpy_n<2>(n, y, S, norm_partials, G, s); break;
-    case 3: launch_multiaxpy_n<3>(n, y, S, norm_partials, G, s); break;
-    case 4: launch_multiaxpy_n<4>(n, y, S, norm_partials, G, s); break;
-    case 5: launch_multiaxpy_n<5>(n, y, S, norm_partials, G, s); break;
-    case 6: launch_multiaxpy_n<6>(n, y, S, norm_partials, G, s); break;
-    case 7: launch_multiaxpy_n<7>(n, y, S, norm_partials, G, s); break;
-    default: launch_multiaxpy_n<8>(n, y, S, norm_partials, G, s); break;
-    }
+    dispatch_nv(nv, [&](auto NVc) { launch_multiaxpy_n<decltype(NVc)::value>(n, y, S, norm_partials, G, s); });
     return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy_dot(size_t n, double *y, const double *const *v, const double *a, int nv,
+                                double *partials, double *stage, double *out, hipStream_t s)
+{
+    if (nv < 1 || nv > kMultiMax) return hipErrorInvalidValue;
+    VecSet S{};
+    for (int i = 0; i < nv; ++i) {
+        S.v[i] = v[i];
+        S.a[i] = a[i];
+    }
+    const int G = vec_grid(n);
+    dispatch_nv(nv, [&](auto NVc) { launch_multiaxpy_dot_n<decltype(NVc)::value>(n, y, S, partials, G, s); });
+    return launch_sum_partials(partials, G, nv + 1, stage, out, s);
 }
 
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, const double *z, double *y, hipStream_t s)
