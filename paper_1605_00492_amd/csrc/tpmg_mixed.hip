@@ -25,10 +25,29 @@ namespace {
 
 constexpr int kMixedKC = 16;
 
-__device__ __forceinline__ double wface_h(const Level<double> &L, const double *c, size_t o, int k)
-{
-    return L.wh[k] * c[o];
-}
+// Buffer descriptors of the four blocks of a mixed vector and of the three
+// face-coefficient arrays, with 32-bit byte offsets: column in the lane
+// offset, k plane in the wave-uniform offset (blocks hold < 2^32 bytes).
+struct MixedRows {
+    Rsrc cE, cN, cU;
+    unsigned oc, oe, ow, on, os, pstride;
+    __device__ MixedRows(const Level<double> &L, unsigned col)
+    {
+        const size_t m = (size_t)L.nz * L.plane;
+        cE = make_rsrc(L.c, m * 8);
+        cN = make_rsrc(L.c + m, m * 8);
+        cU = make_rsrc(L.c + 2 * m, m * 8);
+        const Nbr nb = neighbours(col, L.n, L.plane);
+        oc = col * 8u;
+        oe = nb.e * 8u;
+        ow = nb.w * 8u;
+        on = nb.n * 8u;
+        os = nb.s * 8u;
+        pstride = (unsigned)L.plane * 8u;
+    }
+};
+
+__device__ __forceinline__ double ld(Rsrc r, unsigned voff, unsigned soff) { return bload(double(), r, voff, soff); }
 
 // y = A x.
 __global__ __launch_bounds__(kStreamThreads) void k_mixed_apply(Level<double> L, const double *__restrict__ x,
@@ -37,56 +56,56 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_apply(Level<double> L,
     int col, k0;
     bool active;
     stream_coords<kMixedKC>(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const size_t m = (size_t)nz * plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const double *xE = x, *xN = x + m, *xU = x + 2 * m, *xP = x + 3 * m;
-    double *yE = y, *yN = y + m, *yU = y + 2 * m, *yP = y + 3 * m;
-    const double *cE = L.c, *cN = L.c + m, *cU = L.c + 2 * m;
-    // vertical window: U face below the cell (weight, value)
+    const int nz = L.nz;
+    const size_t m = (size_t)nz * L.plane;
+    const MixedRows R(L, col);
+    const Rsrc xE = make_rsrc(x, m * 8), xN = make_rsrc(x + m, m * 8), xU = make_rsrc(x + 2 * m, m * 8),
+               xP = make_rsrc(x + 3 * m, m * 8);
+    const Rsrc yE = make_rsrc(y, m * 8), yN = make_rsrc(y + m, m * 8), yU = make_rsrc(y + 2 * m, m * 8),
+               yP = make_rsrc(y + 3 * m, m * 8);
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;  // inactive lanes write nothing
+    // vertical window: U face below the cell (weight, value), the cell's own
+    // U face (weight, value) and the pressure of the cell
     double wUm = 0, xUm = 0;
     if (k0 > 0 && k0 - 1 < nz - 1) {
-        const size_t om = (size_t)(k0 - 1) * plane + col;
-        wUm = L.wz[k0 - 1] * cU[om];
-        xUm = xU[om];
+        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
+        wUm = L.wz[k0 - 1] * ld(R.cU, R.oc, sm);
+        xUm = ld(xU, R.oc, sm);
     }
-#pragma unroll 2
+#pragma unroll
     for (int t = 0; t < kMixedKC; ++t) {
         const int k = k0 + t;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const size_t pc = o + col;
-        const double xp = xP[pc];
-        // east faces: own, west neighbour's, east neighbour's
-        const double we = wface_h(L, cE, pc, k), ww = wface_h(L, cE, o + nb.w, k), wee = wface_h(L, cE, o + nb.e, k);
-        const double xe = xE[pc], xw = xE[o + nb.w], xee = xE[o + nb.e];
-        const double ye = xe / we + 0.25 * (xw / sqrt(we * ww) + xee / sqrt(we * wee)) - (xp - xP[o + nb.e]);
-        // north faces
-        const double wn = wface_h(L, cN, pc, k), ws = wface_h(L, cN, o + nb.s, k), wnn = wface_h(L, cN, o + nb.n, k);
-        const double xn = xN[pc], xs = xN[o + nb.s], xnn = xN[o + nb.n];
-        const double yn = xn / wn + 0.25 * (xs / sqrt(wn * ws) + xnn / sqrt(wn * wnn)) - (xp - xP[o + nb.n]);
-        // upper face (none above the top cell)
-        double yu = 0, xu = 0, wu = 0;
-        if (k + 1 < nz) {
-            wu = L.wz[k] * cU[pc];
-            xu = xU[pc];
-            double acc = xu / wu;
-            if (k >= 1) acc += 0.25 * xUm / sqrt(wu * wUm);
-            if (k + 2 < nz) {
-                const double wup = L.wz[k + 1] * cU[pc + plane];
-                acc += 0.25 * xU[pc + plane] / sqrt(wu * wup);
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const double h = L.wh[k];
+            const double xp = ld(xP, R.oc, sk);
+            // east faces: own, west neighbour's, east neighbour's
+            const double we = h * ld(R.cE, R.oc, sk), ww = h * ld(R.cE, R.ow, sk), wee = h * ld(R.cE, R.oe, sk);
+            const double xe = ld(xE, R.oc, sk), xw = ld(xE, R.ow, sk), xee = ld(xE, R.oe, sk);
+            const double ye = xe / we + 0.25 * (xw / sqrt(we * ww) + xee / sqrt(we * wee)) - (xp - ld(xP, R.oe, sk));
+            // north faces
+            const double wn = h * ld(R.cN, R.oc, sk), ws = h * ld(R.cN, R.os, sk), wnn = h * ld(R.cN, R.on, sk);
+            const double xn = ld(xN, R.oc, sk), xs = ld(xN, R.os, sk), xnn = ld(xN, R.on, sk);
+            const double yn = xn / wn + 0.25 * (xs / sqrt(wn * ws) + xnn / sqrt(wn * wnn)) - (xp - ld(xP, R.on, sk));
+            // upper face (none above the top cell)
+            double yu = 0, xu = 0, wu = 0;
+            if (k + 1 < nz) {
+                const unsigned sp = sk + R.pstride;
+                wu = L.wz[k] * ld(R.cU, R.oc, sk);
+                xu = ld(xU, R.oc, sk);
+                double acc = xu / wu;
+                if (k >= 1) acc += 0.25 * xUm / sqrt(wu * wUm);
+                if (k + 2 < nz) acc += 0.25 * ld(xU, R.oc, sp) / sqrt(wu * (L.wz[k + 1] * ld(R.cU, R.oc, sp)));
+                yu = acc - (xp - ld(xP, R.oc, sp));
             }
-            yu = acc - (xp - xP[pc + plane]);
+            const double yp = (xe - xw) + (xn - xs) + (xu - xUm) + L.mu[k] * xp;
+            bstore(ye, yE, oo, sk);
+            bstore(yn, yN, oo, sk);
+            bstore(yu, yU, oo, sk);
+            bstore(yp, yP, oo, sk);
+            wUm = wu;
+            xUm = xu;
         }
-        const double yp = (xe - xw) + (xn - xs) + (xu - xUm) + L.mu[k] * xp;
-        if (active) {
-            yE[pc] = ye;
-            yN[pc] = yn;
-            yU[pc] = yu;
-            yP[pc] = yp;
-        }
-        wUm = wu;
-        xUm = xu;
     }
 }
 
@@ -97,32 +116,34 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_pre1(Level<double> L, 
     int col, k0;
     bool active;
     stream_coords<kMixedKC>(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const size_t m = (size_t)nz * plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const double *rE = r, *rN = r + m, *rU = r + 2 * m, *rP = r + 3 * m;
-    const double *cE = L.c, *cN = L.c + m, *cU = L.c + 2 * m;
+    const int nz = L.nz;
+    const size_t m = (size_t)nz * L.plane;
+    const MixedRows R(L, col);
+    const Rsrc rE = make_rsrc(r, m * 8), rN = make_rsrc(r + m, m * 8), rU = make_rsrc(r + 2 * m, m * 8),
+               rP = make_rsrc(r + 3 * m, m * 8);
+    const Rsrc rt = make_rsrc(t, m * 8), rt32 = make_rsrc(t32, t32 ? m * 4 : 0);
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
+    const unsigned oo32 = active ? R.oc / 2 : 0xFFFFFFFFu;
     double fUm = 0;  // W r on the U face below
     if (k0 > 0 && k0 - 1 < nz - 1) {
-        const size_t om = (size_t)(k0 - 1) * plane + col;
-        fUm = L.wz[k0 - 1] * cU[om] * rU[om];
+        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
+        fUm = L.wz[k0 - 1] * ld(R.cU, R.oc, sm) * ld(rU, R.oc, sm);
     }
-#pragma unroll 4
+#pragma unroll
     for (int tt = 0; tt < kMixedKC; ++tt) {
         const int k = k0 + tt;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const size_t pc = o + col;
-        const double h = L.wh[k];
-        const double fU = (k + 1 < nz) ? L.wz[k] * cU[pc] * rU[pc] : 0.0;
-        const double div = (h * cE[pc] * rE[pc] - h * cE[o + nb.w] * rE[o + nb.w]) +
-                           (h * cN[pc] * rN[pc] - h * cN[o + nb.s] * rN[o + nb.s]) + (fU - fUm);
-        const double tv = rP[pc] - div;
-        if (active) {
-            t[pc] = tv;
-            if (t32) t32[pc] = (float)tv;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const double h = L.wh[k];
+            const double fU = (k + 1 < nz) ? L.wz[k] * ld(R.cU, R.oc, sk) * ld(rU, R.oc, sk) : 0.0;
+            const double div = (h * ld(R.cE, R.oc, sk) * ld(rE, R.oc, sk) - h * ld(R.cE, R.ow, sk) * ld(rE, R.ow, sk)) +
+                               (h * ld(R.cN, R.oc, sk) * ld(rN, R.oc, sk) - h * ld(R.cN, R.os, sk) * ld(rN, R.os, sk)) +
+                               (fU - fUm);
+            const double tv = ld(rP, R.oc, sk) - div;
+            bstore(tv, rt, oo, sk);
+            if (t32) bstore((float)tv, rt32, oo32, sk / 2);
+            fUm = fU;
         }
-        fUm = fU;
     }
 }
 
@@ -134,29 +155,33 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_pre2(Level<double> L, 
     int col, k0;
     bool active;
     stream_coords<kMixedKC>(L, col, k0, active);
-    const int nz = L.nz, plane = L.plane;
-    const size_t m = (size_t)nz * plane;
-    const Nbr nb = neighbours(col, L.n, plane);
-    const double *rE = r, *rN = r + m, *rU = r + 2 * m;
-    double *zE = z, *zN = z + m, *zU = z + 2 * m, *zP = z + 3 * m;
-    const double *cE = L.c, *cN = L.c + m, *cU = L.c + 2 * m;
-    auto Y = [&](size_t q) -> double { return y32 ? (double)y32[q] : y64[q]; };
-#pragma unroll 4
+    const int nz = L.nz;
+    const size_t m = (size_t)nz * L.plane;
+    const MixedRows R(L, col);
+    const Rsrc rE = make_rsrc(r, m * 8), rN = make_rsrc(r + m, m * 8), rU = make_rsrc(r + 2 * m, m * 8);
+    const Rsrc zE = make_rsrc(z, m * 8), zN = make_rsrc(z + m, m * 8), zU = make_rsrc(z + 2 * m, m * 8),
+               zP = make_rsrc(z + 3 * m, m * 8);
+    const bool f32 = y32 != nullptr;
+    const Rsrc ry = f32 ? make_rsrc(y32, m * 4) : make_rsrc(y64, m * 8);
+    auto Y = [&](unsigned voff, unsigned soff) -> double {
+        return f32 ? (double)bload(float(), ry, voff / 2, soff / 2) : bload(double(), ry, voff, soff);
+    };
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
+#pragma unroll
     for (int tt = 0; tt < kMixedKC; ++tt) {
         const int k = k0 + tt;
-        if (k >= nz) break;
-        const size_t o = (size_t)k * plane;
-        const size_t pc = o + col;
-        const double h = L.wh[k];
-        const double yp = Y(pc);
-        const double ze = h * cE[pc] * (rE[pc] + (yp - Y(o + nb.e)));
-        const double zn = h * cN[pc] * (rN[pc] + (yp - Y(o + nb.n)));
-        const double zu = (k + 1 < nz) ? L.wz[k] * cU[pc] * (rU[pc] + (yp - Y(pc + plane))) : 0.0;
-        if (active) {
-            zE[pc] = ze;
-            zN[pc] = zn;
-            zU[pc] = zu;
-            zP[pc] = yp;
+        if (k < nz) {
+            const unsigned sk = (unsigned)k * R.pstride;
+            const double h = L.wh[k];
+            const double yp = Y(R.oc, sk);
+            const double ze = h * ld(R.cE, R.oc, sk) * (ld(rE, R.oc, sk) + (yp - Y(R.oe, sk)));
+            const double zn = h * ld(R.cN, R.oc, sk) * (ld(rN, R.oc, sk) + (yp - Y(R.on, sk)));
+            const double zu =
+                (k + 1 < nz) ? L.wz[k] * ld(R.cU, R.oc, sk) * (ld(rU, R.oc, sk) + (yp - Y(R.oc, sk + R.pstride))) : 0.0;
+            bstore(ze, zE, oo, sk);
+            bstore(zn, zN, oo, sk);
+            bstore(zu, zU, oo, sk);
+            bstore(yp, zP, oo, sk);
         }
     }
 }
