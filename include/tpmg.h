@@ -254,7 +254,8 @@ tpmg_status tpmg_destroy(tpmg_hierarchy *h);
  *   (TPMG_ERR_WORKSPACE otherwise).  info->rel_residual is the final estimate,
  *   info->true_rel_residual = ||b - A x|| / ||b|| recomputed.  Returns TPMG_OK,
  *   TPMG_NOT_CONVERGED (x holds the last iterate), TPMG_ERR_BREAKDOWN or an
- *   argument/device error.  Synchronises `stream`.
+ *   argument/device error; TPMG_ERR_INVALID_ARG when b is not 0 in the U
+ *   slots of the top cells.  Synchronises `stream`.
  */
 #define TPMG_MAX_RESTART 256
 typedef struct {

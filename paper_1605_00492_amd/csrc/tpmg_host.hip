@@ -1064,6 +1064,18 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
     double *x = x_dev;
     const double *b = b_dev;
 
+    {
+        // the U slots of the top cells hold no face: b must be 0 there
+        const size_t plane = (size_t)h->l64[0].plane;
+        const double *top = b + 3 * h->ncell - plane;
+        double tt = 0.0;
+        HIP_TRY(h, launch_multidot(plane, top, &top, 1, W.partials, W.stage, W.out, s));
+        HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        tt = h->dots_host[0];
+        if (tt != 0.0)
+            return fail(h, TPMG_ERR_INVALID_ARG, "b is not 0 in the U slots of the top cells (no face there)");
+    }
     HIP_TRY(h, launch_fill(x, 0.0, M, s));
     HIP_TRY(h, launch_copy(W.w, b, M, s));
     double bb = 0.0;

@@ -134,6 +134,11 @@ def test_edge_cases_and_errors():
     assert info["converged"] and info["iterations"] == 0 and float(x.abs().max()) == 0.0
     x, info = H.mixed_solve(to_dev(cs.b), rtol=1e-14, maxit=3)
     assert not info["converged"] and info["iterations"] == 3 and info["status"] == 1
+    bad = to_dev(cs.b)
+    bad[2, -1, 3, 5] = 1.0                          # no face above the top cell
+    with pytest.raises(tp.TpmgError) as ei:
+        H.mixed_solve(bad, rtol=1e-8)
+    assert ei.value.status == -1
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(tp.TpmgError) as ei:
         _raw_solve(H, to_dev(cs.b), small)
