@@ -249,6 +249,55 @@ def mixed_system(tp, torch, w, dev, args):
     print(json.dumps(out), flush=True)
 
 
+def all_configs(tp, torch, dev, args):
+    """Time per solve (to each workload's rtol) for every workload, FP64 and
+    mixed: setup, solve (median of 5 after 2 warm-ups), iterations, DOF
+    iterations/s and the V-cycle time against its byte model.  On the smaller
+    grids the level data fits the 256 MB last-level cache, so the model
+    bandwidth there is an effective figure, not HBM."""
+    from paper_1605_00492_amd.binding import K_VCYCLE
+
+    import synthetic as syn
+    out = []
+    for name, w in syn.CONFIGS.items():
+        c = torch.from_numpy(w.coefficients()).to(dev)
+        b = torch.from_numpy(w.rhs()).to(dev)
+        kw = dict(dz=w.dz(), a_h=w.a_h, a_z=w.a_z, levels=w.levels, nu=w.nu, omega=w.omega, coarse=w.coarse,
+                  n_coarse=w.n_coarse)
+        for prec in ("fp64", "mixed"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = tp.Hierarchy(c, precision=prec, **kw)
+            torch.cuda.synchronize()
+            setup_ms = (time.perf_counter() - t0) * 1e3
+            for _ in range(2):
+                H.solve(b, rtol=w.rtol)
+            ts = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = H.solve(b, rtol=w.rtol)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            ms = sorted(ts)[2] * 1e3
+            H.profile_enable(True)
+            H.solve(b, rtol=w.rtol)
+            vc_ms, vc_n = H.profile_read(K_VCYCLE)
+            H.profile_enable(False)
+            H.close()
+            vc = vc_ms / max(vc_n, 1)
+            word = 4 if prec == "mixed" else 8
+            row = dict(workload=name, grid=[w.n, w.n, w.nz], dof=w.dof, precision=prec, setup_ms=setup_ms,
+                       solve_ms=ms, iterations=info["iterations"], true_rel_residual=info["true_rel_residual"],
+                       dof_iterations_per_s=w.dof * info["iterations"] / (ms * 1e-3), vcycle_ms=vc,
+                       vcycle_model_GBps=VCYCLE_WORDS * word * w.dof / (vc * 1e-3) / 1e9)
+            out.append(row)
+            log(f"config {row}")
+        del c, b
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large_1024x1024x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="time per solve for every workload, FP64 and mixed")
     ap.add_argument("--mixed-system", action="store_true",
                     help="velocity-pressure system: GMRES with multigrid vs single-level preconditioners")
     ap.add_argument("--robustness", action="store_true",
@@ -282,6 +333,9 @@ def main():
         return
     if args.mixed_system:
         mixed_system(tp, torch, w, dev, args)
+        return
+    if args.configs:
+        all_configs(tp, torch, dev, args)
         return
     log(f"generating {w.name} ({w.dof} DOF)")
     c = torch.from_numpy(w.coefficients()).to(dev)
