@@ -214,12 +214,20 @@ def mixed_system(tp, torch, w, dev, args):
     preconditioner, the pressure block approximated by one multigrid V-cycle
     (FP64 or FP32) or by the single-level method, at nu_CFL = 2 (a_h = 1, the
     workload) and nu_CFL = 8 (a_h = 16, the paper's runs).  GMRES(30) on
-    512^2 x 64 and GMRES(20) on the full grid (memory: 2 (m + 1) mixed vectors)."""
+    512^2 x 64 and GMRES(20) on the full grid (memory: 2 m + 1 mixed vectors).
+    --mixed-only N:A_H:NAME (each part may be *) keeps the matching runs."""
     import numpy as np
 
     import synthetic as syn
     out = {"rtol": 1e-5, "runs": []}
+    only = (args.mixed_only or "*:*:*").split(":")
+
+    def keep(i, v):
+        return only[i] == "*" or only[i] == str(v)
+
     for n, nz, restart in ((512, 64, 30), (w.n, w.nz, 20)):
+        if not keep(0, n):
+            continue
         ww = syn.scaled(w, n, nz=nz, levels=int(round(np.log2(n // 16))) + 1, name=f"{w.name}@{n}x{n}x{nz}")
         c = torch.from_numpy(ww.coefficients()).to(dev)
         b = torch.from_numpy(ww.mixed_rhs()).to(dev)
@@ -227,6 +235,8 @@ def mixed_system(tp, torch, w, dev, args):
             for name, kw in (("mg_fp32", dict(levels=ww.levels, precision="mixed")),
                              ("mg_fp64", dict(levels=ww.levels, precision="fp64")),
                              ("single_level", dict(levels=1, precision="mixed"))):
+                if not (keep(1, int(a_h)) and keep(2, name)):
+                    continue
                 H = tp.Hierarchy(c, dz=ww.dz(), a_h=a_h, a_z=ww.a_z, nu=ww.nu, omega=ww.omega, **kw)
                 ws = torch.empty(H.mixed_workspace_bytes(restart), dtype=torch.uint8, device=dev)
                 H.mixed_solve(b, rtol=1e-5, restart=restart, maxit=300, workspace=ws)
@@ -309,6 +319,9 @@ def main():
                     help="time per solve for every workload, FP64 and mixed")
     ap.add_argument("--mixed-system", action="store_true",
                     help="velocity-pressure system: GMRES with multigrid vs single-level preconditioners")
+    ap.add_argument("--mixed-only", default=None, metavar="N:A_H:NAME",
+                    help="with --mixed-system: only the runs on grid width N, a_h and preconditioner NAME "
+                         "(mg_fp32, mg_fp64, single_level; * matches all)")
     ap.add_argument("--robustness", action="store_true",
                     help="Courant-number and resolution study (single level vs multigrid variants)")
     ap.add_argument("--probe", action="store_true",

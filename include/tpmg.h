@@ -27,9 +27,12 @@
  * FP32 while the outer CG stays FP64.
  *
  * LAYOUTS of device arrays:
- *   TPMG_LAYOUT_LEVEL_MAJOR  (native) cells x[k][j][i], faces c[f][k][j][i]
+ *   TPMG_LAYOUT_LEVEL_MAJOR  cells x[k][j][i], faces c[f][k][j][i]
  *   TPMG_LAYOUT_COLUMN_MAJOR (Sec. 4.3 ordering) cells x[j][i][k], faces c[j][i][k][f]
- * with i fastest in level-major, f in {E=0, N=1, U=2}.  The E face of cell
+ * with i fastest in level-major, f in {E=0, N=1, U=2}.  Internally every
+ * level is stored in tiles of 64 columns (col = j*n + i) whose nz levels are
+ * contiguous, when n*n is a multiple of 64 (otherwise level-major); entry
+ * points convert the caller's arrays on the way in and out.  The E face of cell
  * (i,j,k) joins (i+1 mod n, j, k), the N face joins (i, j+1 mod n, k), the U
  * face joins (i, j, k+1); the U slot of the top cell holds no face (its value
  * is ignored on input and its gradient is 0).
@@ -249,9 +252,12 @@ tpmg_status tpmg_destroy(tpmg_hierarchy *h);
  *   P^{-1}, the V-cycle in the hierarchy's precision; Sec. 5 uses GMRES(30))
  *   from x = 0 until the Arnoldi residual estimate is <= rtol ||b||.
  *   Orthogonalisation: classical Gram-Schmidt, repeated when the first pass
- *   cancels more than a factor 1/sqrt(2) of the norm; fixed-order reductions.  workspace: caller-owned device memory of at least
- *   tpmg_mixed_workspace_bytes(restart) bytes, 256-byte aligned
- *   (TPMG_ERR_WORKSPACE otherwise).  info->rel_residual is the final estimate,
+ *   cancels more than a factor 1/sqrt(2) of the norm; fixed-order reductions.
+ *   The Krylov vectors are kept unnormalised with their scales on the host.
+ *   workspace: caller-owned device memory of at least
+ *   tpmg_mixed_workspace_bytes(restart) bytes (2 restart + 1 mixed vectors
+ *   plus reduction buffers), 256-byte aligned (TPMG_ERR_WORKSPACE otherwise).
+ *   b and x must not alias; b is read throughout and left unchanged.  info->rel_residual is the final estimate,
  *   info->true_rel_residual = ||b - A x|| / ||b|| recomputed.  Returns TPMG_OK,
  *   TPMG_NOT_CONVERGED (x holds the last iterate), TPMG_ERR_BREAKDOWN or an
  *   argument/device error; TPMG_ERR_INVALID_ARG when b is not 0 in the U

@@ -136,6 +136,34 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
     block_partials<1>(vv, out + (size_t)v * kReduceSegs, kReduceSegs, seg);
 }
 
+// Byte offset of cell (col, 0) of a level's tiled storage; level k adds
+// k * tile_width(plane) * sizeof(T) (arrays hold fewer than 2^32 bytes).
+template <typename T>
+__device__ __forceinline__ unsigned cell_off(const Level<T> &L, unsigned col)
+{
+    return (unsigned)cell_base(col, L.plane, L.nz) * (unsigned)sizeof(T);
+}
+
+// Kernels that visit a level's storage element by element (256 threads per
+// workgroup): wavefront w covers elements 64 w .. 64 w + 63, so in the tiled
+// storage it covers one (tile, k) and its division stays scalar.
+__device__ __forceinline__ unsigned storage_wave()
+{
+    return blockIdx.x * 4u + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+// (col, k) of storage element g = 64 w + lane of a level (g < 2^31).
+__device__ __forceinline__ void storage_coords(unsigned g, unsigned w, int plane, int nz, unsigned &col, int &k)
+{
+    if ((plane & 63) == 0) {
+        const unsigned tile = w / (unsigned)nz;
+        k = (int)(w - tile * (unsigned)nz);
+        col = tile * 64u + (g & 63u);
+    } else {
+        k = (int)(g / (unsigned)plane);
+        col = g - (unsigned)k * (unsigned)plane;
+    }
+}
+
 // Streaming stencils: thread = (column, chunk of KC cells along k), blocks
 // of kStreamThreads columns, the k-chunks outermost.
 template <int KC, typename T>
@@ -163,12 +191,12 @@ struct StencilRows {
         rN = make_rsrc(L.c + fstride, fstride * sizeof(T));
         rU = make_rsrc(L.c + 2 * fstride, fstride * sizeof(T));
         const Nbr nb = neighbours(col, L.n, L.plane);
-        oc = col * sizeof(T);
-        oe = nb.e * sizeof(T);
-        ow = nb.w * sizeof(T);
-        on = nb.n * sizeof(T);
-        os = nb.s * sizeof(T);
-        pstride = (unsigned)L.plane * sizeof(T);
+        oc = cell_off<T>(L, col);
+        oe = cell_off<T>(L, nb.e);
+        ow = cell_off<T>(L, nb.w);
+        on = cell_off<T>(L, nb.n);
+        os = cell_off<T>(L, nb.s);
+        pstride = (unsigned)tile_width(L.plane) * sizeof(T);
     }
 };
 

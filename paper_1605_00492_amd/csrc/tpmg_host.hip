@@ -22,7 +22,7 @@ constexpr size_t kAlign = 256;
 
 struct LevelBufs {
     int n = 0, plane = 0;
-    void *c = nullptr;                       // [3][nz][plane]
+    void *c = nullptr;                       // [3][nz * plane], tiled storage
     void *mu = nullptr, *wh = nullptr, *wz = nullptr;  // [nz]
     void *b = nullptr, *A = nullptr, *B = nullptr, *E = nullptr;  // level vectors
 };
@@ -325,8 +325,9 @@ tpmg_status vcycle(const tpmg_hierarchy *h, const T *b, T *out, hipStream_t s)
 
 // ---- host factorisation of the coarsest operator (direct mode) -----------------
 
-// Dense H on the coarsest level (level-major cell order), assembled from the
-// level's face coefficients and scalars.
+// Dense H on the coarsest level, rows and columns in the level's storage
+// order (so the dense inverse applies directly to stored vectors), assembled
+// from the level's face coefficients and scalars.
 void assemble_dense(const std::vector<double> &c, const std::vector<double> &mu, const std::vector<double> &wh,
                     const std::vector<double> &wz, int n, int nz, std::vector<double> &A)
 {
@@ -337,7 +338,7 @@ void assemble_dense(const std::vector<double> &c, const std::vector<double> &mu,
     auto idx = [&](int i, int j, int k) -> size_t {
         i = (i % n + n) % n;
         j = (j % n + n) % n;
-        return (size_t)k * plane + (size_t)j * n + i;
+        return cell_index((size_t)j * n + i, k, plane, nz);
     };
     auto couple = [&](size_t p, size_t q, double w) {
         A[p * m + p] += w;
@@ -453,11 +454,70 @@ tpmg_status precondition(tpmg_hierarchy *h, hipStream_t s)
     return vcycle<double>(h, h->r, h->z, s);
 }
 
+// The component entry points take the caller's level-major vectors and stage
+// them in the level's storage order through the CG vectors r, z, p0, p1
+// (free outside tpmg_solve; each holds a level-0 FP64 vector).
+tpmg_status stage_in(const tpmg_hierarchy *h, const void *src, void *dst, int level, int elem, hipStream_t s)
+{
+    HIP_TRY(const_cast<tpmg_hierarchy *>(h),
+            launch_cells_in(src, TPMG_LAYOUT_LEVEL_MAJOR, dst, nullptr, h->l64[level].plane, h->nz, elem, s));
+    return TPMG_OK;
+}
+
+tpmg_status stage_out(const tpmg_hierarchy *h, const void *src, void *dst, int level, int elem, hipStream_t s)
+{
+    HIP_TRY(const_cast<tpmg_hierarchy *>(h),
+            launch_cells_out(src, dst, TPMG_LAYOUT_LEVEL_MAJOR, h->l64[level].plane, h->nz, elem, s));
+    return TPMG_OK;
+}
+
 template <typename T>
 tpmg_status smooth_impl(const tpmg_hierarchy *h, int level, const void *u, const void *b, void *out,
                                hipStream_t s)
 {
-    return sweep<T>(h, level, u ? SWEEP_GENERAL : SWEEP_ZERO, (const T *)u, (const T *)b, (T *)out, nullptr, s);
+    tpmg_status st;
+    T *us = (T *)h->r, *bs = (T *)h->z, *os = (T *)h->p0;
+    if (u && (st = stage_in(h, u, us, level, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = stage_in(h, b, bs, level, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = sweep<T>(h, level, u ? SWEEP_GENERAL : SWEEP_ZERO, u ? us : nullptr, bs, os, nullptr, s)) != TPMG_OK)
+        return st;
+    return stage_out(h, os, out, level, sizeof(T), s);
+}
+
+template <typename T>
+tpmg_status resid_restrict_impl(const tpmg_hierarchy *h, int level, const void *u, const void *b, void *bc,
+                                hipStream_t s)
+{
+    tpmg_status st;
+    T *us = (T *)h->r, *bs = (T *)h->z, *os = (T *)h->p0;
+    if ((st = stage_in(h, u, us, level, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = stage_in(h, b, bs, level, sizeof(T), s)) != TPMG_OK) return st;
+    HIP_TRY(const_cast<tpmg_hierarchy *>(h), launch_resid_restrict<T>(level_view<T>(h, level), us, bs, os, s));
+    return stage_out(h, os, bc, level + 1, sizeof(T), s);
+}
+
+template <typename T>
+tpmg_status prolong_smooth_impl(const tpmg_hierarchy *h, int level, const void *u, const void *ec, const void *b,
+                                void *out, hipStream_t s)
+{
+    tpmg_status st;
+    T *us = (T *)h->r, *es = (T *)h->z, *bs = (T *)h->p0, *os = (T *)h->p1;
+    if ((st = stage_in(h, u, us, level, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = stage_in(h, ec, es, level + 1, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = stage_in(h, b, bs, level, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = sweep<T>(h, level, SWEEP_PROLONG, us, bs, os, es, s)) != TPMG_OK) return st;
+    return stage_out(h, os, out, level, sizeof(T), s);
+}
+
+template <typename T>
+tpmg_status coarse_solve_impl(const tpmg_hierarchy *h, const void *b, void *u, hipStream_t s)
+{
+    tpmg_status st;
+    const int l = h->L - 1;
+    T *bs = (T *)h->r, *os = (T *)h->z;
+    if ((st = stage_in(h, b, bs, l, sizeof(T), s)) != TPMG_OK) return st;
+    if ((st = coarse_solve<T>(h, bs, os, s)) != TPMG_OK) return st;
+    return stage_out(h, os, u, l, sizeof(T), s);
 }
 
 }  // namespace
@@ -612,18 +672,13 @@ tpmg_status tpmg_apply_operator(const tpmg_hierarchy *h, int32_t level, int32_t 
     hipStream_t s = as_stream(stream);
     const int elem = fp32 ? 4 : 8;
     const int plane = h->l64[level].plane;
-    const void *x = x_dev;
-    void *y = y_dev;
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
-        HIP_TRY(hm, launch_cells_to_level(x_dev, h->stage0, plane, h->nz, elem, s));
-        x = h->stage0;
-        y = h->stage1;
-    }
+    void *x = h->stage0, *y = h->stage1;
+    HIP_TRY(hm, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, elem, s));
     if (fp32)
         HIP_TRY(hm, launch_apply<float>(level_view<float>(h, level), (const float *)x, (float *)y, s));
     else
         HIP_TRY(hm, launch_apply<double>(level_view<double>(h, level), (const double *)x, (double *)y, s));
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(hm, launch_cells_to_column(y, y_dev, plane, h->nz, elem, s));
+    HIP_TRY(hm, launch_cells_out(y, y_dev, layout, plane, h->nz, elem, s));
     return TPMG_OK;
 }
 
@@ -640,16 +695,11 @@ tpmg_status tpmg_vcycle(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev
     hipStream_t s = as_stream(stream);
     const int elem = fp32 ? 4 : 8;
     const int plane = h->l64[0].plane;
-    const void *b = b_dev;
-    void *z = z_dev;
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
-        HIP_TRY(hm, launch_cells_to_level(b_dev, h->stage0, plane, h->nz, elem, s));
-        b = h->stage0;
-        z = h->stage1;
-    }
+    void *b = h->stage0, *z = h->stage1;
+    HIP_TRY(hm, launch_cells_in(b_dev, layout, b, nullptr, plane, h->nz, elem, s));
     st = fp32 ? vcycle<float>(h, (const float *)b, (float *)z, s) : vcycle<double>(h, (const double *)b, (double *)z, s);
     if (st != TPMG_OK) return st;
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(hm, launch_cells_to_column(z, z_dev, plane, h->nz, elem, s));
+    HIP_TRY(hm, launch_cells_out(z, z_dev, layout, plane, h->nz, elem, s));
     return TPMG_OK;
 }
 
@@ -671,26 +721,25 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     const Level<double> L0 = level_view<double>(h, 0);
     const int flex = opts->flexible;
 
-    const double *b = b_dev;
-    double *x = x_dev;
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) {
-        HIP_TRY(h, launch_cells_to_level(b_dev, h->stage0, plane, h->nz, 8, s));
-        b = h->stage0;
-        x = h->stage1;
-        if (opts->x0_nonzero) HIP_TRY(h, launch_cells_to_level(x_dev, x, plane, h->nz, 8, s));
-    }
+    // b and x in the level's storage order (stage0, stage1); with a zero
+    // initial guess the conversion of b also writes r = b.
+    double *b = h->stage0, *x = h->stage1;
+    HIP_TRY(h, launch_cells_in(b_dev, layout, b, opts->x0_nonzero ? nullptr : h->r, plane, h->nz, 8, s));
+    if (opts->x0_nonzero) HIP_TRY(h, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, 8, s));
     HIP_TRY(h, launch_fill((double *)h->sc, 0.0, sizeof(Scalars) / sizeof(double), s));
     int G = 0;
     if (opts->x0_nonzero) {
         HIP_TRY(h, launch_residual(L0, x, b, h->r, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
+        HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
     } else {
+        // r = b: one dot gives both (b, b) and (r, r)
         HIP_TRY(h, launch_fill(x, 0.0, n, s));
-        HIP_TRY(h, launch_copy(h->r, b, n, s));
-        HIP_TRY(h, launch_dot(n, h->r, h->r, nullptr, h->partials, &G, s));
+        HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
+        if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
     }
-    if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
-    HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
-    if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
     if ((st = read_scalars(h, s)) != TPMG_OK) return st;
     const double bnorm = std::sqrt(h->sc_host->bb);
     double rnorm = std::sqrt(h->sc_host->rr);
@@ -762,7 +811,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         info->rel_residual = rel;
         info->true_rel_residual = bnorm > 0 ? std::sqrt(h->sc_host->tt) / bnorm : 0.0;
     }
-    if (layout == TPMG_LAYOUT_COLUMN_MAJOR) HIP_TRY(h, launch_cells_to_column(x, x_dev, plane, h->nz, 8, s));
+    HIP_TRY(h, launch_cells_out(x, x_dev, layout, plane, h->nz, 8, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     return result;
 }
@@ -817,13 +866,8 @@ tpmg_status tpmg_residual_restrict(const tpmg_hierarchy *h, int32_t level, int32
     if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {u_dev, b_dev, b_coarse_dev})) != TPMG_OK)
         return st;
     hipStream_t s = as_stream(stream);
-    if (fp32)
-        HIP_TRY(hm, launch_resid_restrict<float>(level_view<float>(h, level), (const float *)u_dev,
-                                                 (const float *)b_dev, (float *)b_coarse_dev, s));
-    else
-        HIP_TRY(hm, launch_resid_restrict<double>(level_view<double>(h, level), (const double *)u_dev,
-                                                  (const double *)b_dev, (double *)b_coarse_dev, s));
-    return TPMG_OK;
+    return fp32 ? resid_restrict_impl<float>(h, level, u_dev, b_dev, b_coarse_dev, s)
+                : resid_restrict_impl<double>(h, level, u_dev, b_dev, b_coarse_dev, s);
 }
 
 tpmg_status tpmg_prolong_smooth(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *u_dev,
@@ -838,11 +882,8 @@ tpmg_status tpmg_prolong_smooth(const tpmg_hierarchy *h, int32_t level, int32_t 
         return st;
     if (u_dev == u_out_dev || b_dev == u_out_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "output must not alias inputs");
     hipStream_t s = as_stream(stream);
-    if (fp32)
-        return sweep<float>(h, level, SWEEP_PROLONG, (const float *)u_dev, (const float *)b_dev, (float *)u_out_dev,
-                            (const float *)e_coarse_dev, s);
-    return sweep<double>(h, level, SWEEP_PROLONG, (const double *)u_dev, (const double *)b_dev, (double *)u_out_dev,
-                         (const double *)e_coarse_dev, s);
+    return fp32 ? prolong_smooth_impl<float>(h, level, u_dev, e_coarse_dev, b_dev, u_out_dev, s)
+                : prolong_smooth_impl<double>(h, level, u_dev, e_coarse_dev, b_dev, u_out_dev, s);
 }
 
 tpmg_status tpmg_coarse_solve(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev, void *u_dev, void *stream)
@@ -853,8 +894,7 @@ tpmg_status tpmg_coarse_solve(const tpmg_hierarchy *h, int32_t fp32, const void 
     if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {b_dev, u_dev})) != TPMG_OK) return st;
     if (b_dev == u_dev) return fail(hm, TPMG_ERR_INVALID_ARG, "b and u must not alias");
     hipStream_t s = as_stream(stream);
-    return fp32 ? coarse_solve<float>(h, (const float *)b_dev, (float *)u_dev, s)
-                : coarse_solve<double>(h, (const double *)b_dev, (double *)u_dev, s);
+    return fp32 ? coarse_solve_impl<float>(h, b_dev, u_dev, s) : coarse_solve_impl<double>(h, b_dev, u_dev, s);
 }
 
 tpmg_status tpmg_level_coefficients(const tpmg_hierarchy *h, int32_t level, int32_t fp32, void *c_out_dev,
@@ -866,8 +906,11 @@ tpmg_status tpmg_level_coefficients(const tpmg_hierarchy *h, int32_t level, int3
     if (level < 0 || level >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
     if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_ptrs(h, {c_out_dev})) != TPMG_OK) return st;
     const LevelBufs &B = fp32 ? h->l32[level] : h->l64[level];
-    const size_t bytes = 3 * (size_t)B.plane * h->nz * (fp32 ? 4 : 8);
-    HIP_TRY(hm, hipMemcpyAsync(c_out_dev, B.c, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+    const int elem = fp32 ? 4 : 8;
+    const size_t bytes = (size_t)B.plane * h->nz * elem;
+    for (int f = 0; f < 3; ++f)
+        HIP_TRY(hm, launch_cells_out((const char *)B.c + f * bytes, (char *)c_out_dev + f * bytes,
+                                     TPMG_LAYOUT_LEVEL_MAJOR, B.plane, h->nz, elem, as_stream(stream)));
     return TPMG_OK;
 }
 
@@ -926,11 +969,11 @@ tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t byte
 namespace {
 
 struct MixedWs {
-    double *V = nullptr, *Z = nullptr, *w = nullptr, *partials = nullptr, *stage = nullptr, *out = nullptr;
+    double *V = nullptr, *Z = nullptr, *partials = nullptr, *stage = nullptr, *out = nullptr;
     size_t M = 0;
 };
 
-// Carve the GMRES workspace: V (restart + 1 vectors), Z (restart), w, partial
+// Carve the GMRES workspace: V (restart + 1 vectors), Z (restart), partial
 // sums, reduction stage and results.  With base == nullptr only the size.
 size_t plan_mixed(const tpmg_hierarchy *h, int restart, char *base, MixedWs *W)
 {
@@ -945,21 +988,21 @@ size_t plan_mixed(const tpmg_hierarchy *h, int restart, char *base, MixedWs *W)
     W->M = M;
     W->V = take((size_t)(restart + 1) * M * sizeof(double));
     W->Z = take((size_t)restart * M * sizeof(double));
-    W->w = take(M * sizeof(double));
     W->partials = take((size_t)(kMultiMax + 1) * kMaxPartials * sizeof(double));
     W->stage = take((size_t)(kMultiMax + 1) * kReduceSegs * sizeof(double));
     W->out = take((size_t)(kMultiMax + 1) * sizeof(double));
     return (off + kAlign - 1) / kAlign * kAlign;
 }
 
-// z = P^{-1} r: t = r_p - D W r_u, z_p = V t (hierarchy precision), z_u = W (r_u + D^T z_p).
-tpmg_status mixed_precondition(tpmg_hierarchy *h, const double *r, double *z, bool fp32, hipStream_t s)
+// z = P^{-1} (a r): t = a (r_p - D W r_u), z_p = V t (hierarchy precision),
+// z_u = W (a r_u + D^T z_p).
+tpmg_status mixed_precondition(tpmg_hierarchy *h, const double *r, double a, double *z, bool fp32, hipStream_t s)
 {
     const Level<double> L0 = level_view<double>(h, 0);
-    HIP_TRY(h, launch_mixed_pre1(L0, r, h->r, fp32 ? h->r32 : nullptr, s));
+    HIP_TRY(h, launch_mixed_pre1(L0, r, a, h->r, fp32 ? h->r32 : nullptr, s));
     tpmg_status st = fp32 ? vcycle<float>(h, h->r32, h->z32, s) : vcycle<double>(h, h->r, h->z, s);
     if (st != TPMG_OK) return st;
-    HIP_TRY(h, launch_mixed_pre2(L0, r, fp32 ? nullptr : h->z, fp32 ? h->z32 : nullptr, z, s));
+    HIP_TRY(h, launch_mixed_pre2(L0, r, a, fp32 ? nullptr : h->z, fp32 ? h->z32 : nullptr, z, s));
     return TPMG_OK;
 }
 
@@ -1037,7 +1080,7 @@ tpmg_status tpmg_mixed_precondition(const tpmg_hierarchy *hc, int32_t fp32, cons
         (st = check_mixed_level(h)) != TPMG_OK)
         return st;
     if ((const void *)r_dev == (const void *)z_dev) return fail(h, TPMG_ERR_INVALID_ARG, "r and z must not alias");
-    return mixed_precondition(h, r_dev, z_dev, fp32 == 1, as_stream(stream));
+    return mixed_precondition(h, r_dev, 1.0, z_dev, fp32 == 1, as_stream(stream));
 }
 
 tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_dev, void *workspace_dev,
@@ -1077,14 +1120,16 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
             return fail(h, TPMG_ERR_INVALID_ARG, "b is not 0 in the U slots of the top cells (no face there)");
     }
     HIP_TRY(h, launch_fill(x, 0.0, M, s));
-    HIP_TRY(h, launch_copy(W.w, b, M, s));
     double bb = 0.0;
     if ((st = mixed_dots(h, W, b, &b, 1, &bb, s)) != TPMG_OK) return st;
     const double bnorm = std::sqrt(bb);
     if (opts->history) opts->history[0] = bnorm > 0.0 ? 1.0 : 0.0;
-    std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), c(R + 1);
-    std::vector<const double *> vptr(R + 2), zptr(R);
-    std::vector<double> coef(R + 1);
+    std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1), y(R), hcol(R + 1), c(R + 2);
+    // Krylov basis stored unnormalised: the j-th basis vector is sc[j] * vptr[j]
+    // (the scales are applied in the dots, the updates and the
+    // preconditioner, which saves a scaling pass over every new vector).
+    std::vector<const double *> vptr(R + 1), zptr(R);
+    std::vector<double> coef(R + 1), sc(R + 1);
     for (int i = 0; i <= R; ++i) vptr[i] = W.V + (size_t)i * M;
     for (int i = 0; i < R; ++i) zptr[i] = W.Z + (size_t)i * M;
     int it = 0;
@@ -1097,63 +1142,62 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
         converged = true;
         est = 0.0;
     }
+    double beta = bnorm;
+    vptr[0] = b;  // first cycle: the residual is b itself
     while (!converged && result == TPMG_NOT_CONVERGED && it < opts->maxit) {
-        double rr = 0.0;
-        const double *wp = W.w;
-        if ((st = mixed_dots(h, W, W.w, &wp, 1, &rr, s)) != TPMG_OK) return st;
-        const double beta = std::sqrt(rr);
         if (beta <= opts->rtol * bnorm) {
             converged = true;
             est = beta / bnorm;
             break;
         }
-        HIP_TRY(h, launch_axpby(M, 1.0 / beta, W.w, 0.0, nullptr, W.V, s));
+        sc[0] = 1.0 / beta;
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jj = 0;
         bool conv = false;
         for (int j = 0; j < R && it < opts->maxit; ++j) {
             double *zj = W.Z + (size_t)j * M;
-            if ((st = mixed_precondition(h, vptr[j], zj, fp32, s)) != TPMG_OK) return st;
-            HIP_TRY(h, launch_mixed_apply(L0, zj, W.w, s));
+            double *wj = W.V + (size_t)(j + 1) * M;  // becomes basis vector j + 1
+            if ((st = mixed_precondition(h, vptr[j], sc[j], zj, fp32, s)) != TPMG_OK) return st;
+            HIP_TRY(h, launch_mixed_apply(L0, zj, wj, s));
             // classical Gram-Schmidt with selective reorthogonalisation: a
             // second pass only when the first one cancels more than a factor
             // 1/sqrt(2) of the norm of w (the "twice is enough" criterion)
-            std::fill(hcol.begin(), hcol.end(), 0.0);
-            double hn2 = 0.0;
-            vptr[j + 1] = W.w;  // (w, w) rides along with the first-pass dots
-            if ((st = mixed_dots(h, W, W.w, vptr.data(), j + 2, c.data(), s)) != TPMG_OK) return st;
-            vptr[j + 1] = W.V + (size_t)(j + 1) * M;
+            vptr[j + 1] = wj;  // (w, w) rides along with the first-pass dots
+            if ((st = mixed_dots(h, W, wj, vptr.data(), j + 2, c.data(), s)) != TPMG_OK) return st;
             const double ww = c[j + 1];
+            double hn2 = 0.0;
             for (int i = 0; i <= j; ++i) {
-                hcol[i] = c[i];
-                coef[i] = -c[i];
+                hcol[i] = c[i] * sc[i];
+                coef[i] = -hcol[i] * sc[i];
             }
             if (j + 1 <= kMultiMax) {
                 // first update fused with the second pass's dots and the norm
-                HIP_TRY(h, launch_multiaxpy_dot(M, W.w, vptr.data(), coef.data(), j + 1, W.partials, W.stage, W.out,
+                HIP_TRY(h, launch_multiaxpy_dot(M, wj, vptr.data(), coef.data(), j + 1, W.partials, W.stage, W.out,
                                                 s));
                 HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
                 HIP_TRY(h, hipStreamSynchronize(s));
                 for (int i = 0; i <= j; ++i) c[i] = h->dots_host[i];
                 hn2 = h->dots_host[j + 1];
-            } else if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) {
+            } else if ((st = mixed_axpys(h, W, wj, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) {
                 return st;
             }
             if (!(hn2 > 0.5 * ww)) {
-                if (j + 1 > kMultiMax && (st = mixed_dots(h, W, W.w, vptr.data(), j + 1, c.data(), s)) != TPMG_OK)
+                if (j + 1 > kMultiMax && (st = mixed_dots(h, W, wj, vptr.data(), j + 1, c.data(), s)) != TPMG_OK)
                     return st;
                 for (int i = 0; i <= j; ++i) {
-                    hcol[i] += c[i];
-                    coef[i] = -c[i];
+                    const double hi = c[i] * sc[i];
+                    hcol[i] += hi;
+                    coef[i] = -hi * sc[i];
                 }
-                if ((st = mixed_axpys(h, W, W.w, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) return st;
+                if ((st = mixed_axpys(h, W, wj, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) return st;
             }
             const double hn = std::sqrt(hn2);
             if (!std::isfinite(hn)) {
                 result = fail(h, TPMG_ERR_BREAKDOWN, "non-finite Arnoldi vector");
                 break;
             }
+            sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
             for (int i = 0; i <= j; ++i) H[(size_t)i * R + j] = hcol[i];
             H[(size_t)(j + 1) * R + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -1177,7 +1221,6 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
                 conv = true;
                 break;
             }
-            HIP_TRY(h, launch_axpby(M, 1.0 / hn, W.w, 0.0, nullptr, W.V + (size_t)(j + 1) * M, s));
         }
         if (result != TPMG_NOT_CONVERGED) break;
         for (int i = jj - 1; i >= 0; --i) {
@@ -1190,16 +1233,23 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
             converged = true;
             break;
         }
-        HIP_TRY(h, launch_mixed_apply(L0, x, W.w, s));
-        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, W.w, W.w, s));
+        // restart from the true residual, computed into basis slot 0
+        double *r0 = W.V;
+        HIP_TRY(h, launch_mixed_apply(L0, x, r0, s));
+        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, r0, r0, s));
+        vptr[0] = r0;
+        double rr = 0.0;
+        if ((st = mixed_dots(h, W, r0, vptr.data(), 1, &rr, s)) != TPMG_OK) return st;
+        beta = std::sqrt(rr);
     }
     if (converged) result = TPMG_OK;
     if (info) {
-        HIP_TRY(h, launch_mixed_apply(L0, x, W.w, s));
-        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, W.w, W.w, s));
+        double *r = W.V;  // the basis is no longer needed
+        HIP_TRY(h, launch_mixed_apply(L0, x, r, s));
+        HIP_TRY(h, launch_axpby(M, 1.0, b, -1.0, r, r, s));
         double tt = 0.0;
-        const double *wp = W.w;
-        if ((st = mixed_dots(h, W, W.w, &wp, 1, &tt, s)) != TPMG_OK) return st;
+        const double *rp = r;
+        if ((st = mixed_dots(h, W, r, &rp, 1, &tt, s)) != TPMG_OK) return st;
         info->iterations = it;
         info->converged = converged ? 1 : 0;
         info->rel_residual = est;

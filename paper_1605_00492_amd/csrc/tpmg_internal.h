@@ -9,14 +9,35 @@
 
 namespace tpmg {
 
-// One multigrid level as the kernels see it.  Level-major storage:
-// cell (i, j, k) at k*plane + j*n + i; faces c[f][k][j][i], f in {E, N, U}.
+// Storage of every cell array of a level (the hierarchy's vectors and each
+// of its three face arrays).  Columns col = j*n + i are grouped into tiles
+// of W consecutive columns; a tile stores its nz levels one after the other,
+// W values per level:
+//   cell (col, k) at (col / W) * nz * W + k * W + col % W,
+// with W = 64 when the plane is a multiple of 64 (a wavefront's 64 lanes
+// read 256 or 512 contiguous bytes per level, and stepping k moves to the
+// next contiguous segment), otherwise W = plane (plain level-major order).
+// Any 64 aligned consecutive columns of one level are contiguous in both this
+// and the level-major order, so converting kernels stay coalesced.
+__host__ __device__ inline int tile_width(int plane) { return (plane & 63) == 0 ? 64 : plane; }
+// index of (col, 0); (col, k) is at cell_base + k * tile_width(plane)
+__host__ __device__ inline size_t cell_base(size_t col, int plane, int nz)
+{
+    return (plane & 63) == 0 ? (col >> 6) * (size_t)nz * 64 + (col & 63) : col;
+}
+__host__ __device__ inline size_t cell_index(size_t col, int k, int plane, int nz)
+{
+    return cell_base(col, plane, nz) + (size_t)k * tile_width(plane);
+}
+
+// One multigrid level as the kernels see it (cells and faces in the tiled
+// storage above; faces c[f] for f in {E, N, U}, each an nz * plane array).
 template <typename T>
 struct Level {
     int n;          // columns per side
     int nz;         // cells per column
     int plane;      // n * n
-    const T *c;     // [3][nz][plane]; U slot of the top cell holds 0
+    const T *c;     // [3][nz * plane]; U slot of the top cell holds 0
     const T *mu;    // [nz]  mass 4^l s_k
     const T *wh;    // [nz]  horizontal factor a_h s_k
     const T *wz;    // [nz]  vertical factor 4^l a_z / t_{k+1/2}; wz[nz-1] = 0
@@ -81,6 +102,12 @@ hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, float 
                               hipStream_t s);
 hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
+// Caller's cells (layout 0 level-major, 1 column-major; elem = 4 or 8 bytes)
+// <-> the tiled storage of a level with this plane; cells_in also writes a
+// second copy to dst2 when given.
+hipError_t launch_cells_in(const void *src, int layout, void *dst, void *dst2, int plane, int nz, int elem,
+                           hipStream_t s);
+hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, int nz, int elem, hipStream_t s);
 // level-major <-> column-major cell transposes (elem = 4 or 8 bytes)
 hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, int elem,
                                  hipStream_t s);
@@ -112,11 +139,11 @@ hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream
 // Vectors of the outer GMRES combined per kernel launch.
 constexpr int kMultiMax = 16;
 hipError_t launch_mixed_apply(const Level<double> &L, const double *x, double *y, hipStream_t s);
-// t = r_p - D W r_u (and fl32(t) into t32 when given)
-hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double *t, float *t32, hipStream_t s);
-// z_u = W (r_u + D^T y), z_p = y, y from y64 or y32
-hipError_t launch_mixed_pre2(const Level<double> &L, const double *r, const double *y64, const float *y32, double *z,
-                             hipStream_t s);
+// t = a (r_p - D W r_u) (and fl32(t) into t32 when given)
+hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double a, double *t, float *t32, hipStream_t s);
+// z_u = W (a r_u + D^T y), z_p = y, y from y64 or y32
+hipError_t launch_mixed_pre2(const Level<double> &L, const double *r, double a, const double *y64, const float *y32,
+                             double *z, hipStream_t s);
 // out[i] = (w, v_i), i < nv <= kMultiMax, fixed-order reductions
 hipError_t launch_multidot(size_t n, const double *w, const double *const *v, int nv, double *partials,
                            double *stage, double *out, hipStream_t s);

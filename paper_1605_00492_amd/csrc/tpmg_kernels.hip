@@ -5,8 +5,11 @@
 //
 // Every kernel is bandwidth-bound (about 0.5 flop/byte), so the design is
 // about HBM traffic, not the matrix cores:
-//  * level-major storage: a wavefront holds 64 consecutive columns of one
-//    level plane, so every load of a k-plane row is one coalesced segment;
+//  * tiled storage (64 columns per tile, the tile's levels contiguous): a
+//    wavefront holds the 64 columns of a tile, so every load of a level is
+//    one 256- or 512-byte segment and stepping k reads the next segment
+//    (sequential streams per wavefront; the level-major order, whose levels
+//    lie a whole plane apart, streamed 10 % slower in the sweep);
 //  * horizontal neighbours come through the caches from the same or the
 //    adjacent rows, which the XCD-aware block order keeps in one XCD's L2;
 //  * vertical neighbours live in registers (sliding window along k);
@@ -219,20 +222,22 @@ __global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ 
     const Rsrc rN = make_rsrc(L.c + fstride, fstride * S);
     const Rsrc rU = make_rsrc(L.c + 2 * fstride, fstride * S);
     const Rsrc ru = make_rsrc(u, MODE == SWEEP_ZERO ? 0 : fstride * S);
-    const unsigned oc = cc * S, oe = nb.e * S, ow = nb.w * S, on = nb.n * S, os = nb.s * S;
-    const unsigned pstride = (unsigned)plane * S;
+    const unsigned oc = cell_off(L, cc), oe = cell_off(L, nb.e), ow = cell_off(L, nb.w), on = cell_off(L, nb.n),
+                   os = cell_off(L, nb.s);
+    const unsigned pstride = (unsigned)tile_width(plane) * S;
 
     // Prolongation: every u value read is u + e(parent) (injection).
     const int nc = L.n >> 1, planec = nc * nc;
     const Rsrc re = make_rsrc(ec, MODE == SWEEP_PROLONG ? (size_t)nz * planec * S : 0);
-    const unsigned cstride = (unsigned)planec * S;
+    const unsigned cstride = (unsigned)tile_width(planec) * S;
     unsigned pc = 0, pe = 0, pw = 0, pn = 0, ps = 0;
     if (MODE == SWEEP_PROLONG) {
-        pc = parent(cc, L.n) * S;
-        pe = parent(nb.e, L.n) * S;
-        pw = parent(nb.w, L.n) * S;
-        pn = parent(nb.n, L.n) * S;
-        ps = parent(nb.s, L.n) * S;
+        auto poff = [&](int q) { return (unsigned)cell_base(parent(q, L.n), planec, nz) * S; };
+        pc = poff(cc);
+        pe = poff(nb.e);
+        pw = poff(nb.w);
+        pn = poff(nb.n);
+        ps = poff(nb.s);
     }
     auto U = [&](int k, unsigned o, unsigned po) -> T {
         T v = bload(T(), ru, o, (unsigned)k * pstride);
@@ -405,20 +410,22 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
     const int ie = (i0 + 2 == n) ? 0 : i0 + 2;
     const int js = (j0 == 0) ? n - 1 : j0 - 1;
     const int jn = (j0 + 2 == n) ? 0 : j0 + 2;
-    // the four children a=(i0,j0) b=(i0+1,j0) c=(i0,j0+1) d=(i0+1,j0+1), byte offsets
-    const unsigned q0 = (j0 * n + i0) * S, q1 = q0 + S, q2 = q0 + n * S, q3 = q2 + S;
-    const unsigned qw0 = (j0 * n + iw) * S, qw1 = qw0 + n * S;   // west of a, c
-    const unsigned qe0 = (j0 * n + ie) * S, qe1 = qe0 + n * S;   // east of b, d
-    const unsigned qs0 = (js * n + i0) * S, qs1 = qs0 + S;       // south of a, b
-    const unsigned qn0 = (jn * n + i0) * S, qn1 = qn0 + S;       // north of c, d
+    // the four children a=(i0,j0) b=(i0+1,j0) c=(i0,j0+1) d=(i0+1,j0+1), byte
+    // offsets (i0 is even, so a and b, c and d share a 64-column tile)
+    auto off = [&](int i, int j) { return cell_off(L, (unsigned)(j * n + i)); };
+    const unsigned q0 = off(i0, j0), q1 = q0 + S, q2 = off(i0, j0 + 1), q3 = q2 + S;
+    const unsigned qw0 = off(iw, j0), qw1 = off(iw, j0 + 1);    // west of a, c
+    const unsigned qe0 = off(ie, j0), qe1 = off(ie, j0 + 1);    // east of b, d
+    const unsigned qs0 = off(i0, js), qs1 = qs0 + S;            // south of a, b
+    const unsigned qn0 = off(i0, jn), qn1 = qn0 + S;            // north of c, d
     const unsigned q[4] = {q0, q1, q2, q3};
     const size_t fbytes = (size_t)nz * plane * S;
     const Rsrc ru = make_rsrc(u, fbytes), rb = make_rsrc(b, fbytes);
     const Rsrc rE = make_rsrc(L.c, fbytes), rN = make_rsrc(L.c + (size_t)nz * plane, fbytes);
     const Rsrc rU = make_rsrc(L.c + 2 * (size_t)nz * plane, fbytes);
     const Rsrc rc = make_rsrc(bc, (size_t)nz * planec * S);
-    const unsigned pstride = (unsigned)plane * S, cstride = (unsigned)planec * S;
-    const unsigned oo = active ? (unsigned)ccol * S : 0xFFFFFFFFu;
+    const unsigned pstride = (unsigned)tile_width(plane) * S, cstride = (unsigned)tile_width(planec) * S;
+    const unsigned oo = active ? (unsigned)cell_base(ccol, planec, nz) * S : 0xFFFFFFFFu;
 
     T um[4], uc[4], wD[4];
 #pragma unroll
@@ -481,23 +488,26 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(const T *__restrict__ ainv,
 
 // ---- setup kernels ---------------------------------------------------------
 
-// Level l+1 faces from level l: mean of the fine faces covering each coarse face.
+// Level l+1 faces from level l: mean of the fine faces covering each coarse
+// face.  Thread = one coarse cell, in storage order.
 __global__ __launch_bounds__(256) void k_coarsen(Level<double> F, double *__restrict__ cc,
                                                  float *__restrict__ cc32)
 {
     const int n = F.n, nz = F.nz, nc = n >> 1, planec = nc * nc;
-    const size_t total = (size_t)planec * nz;
-    const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const unsigned total = (unsigned)planec * nz;
+    const unsigned w = storage_wave(), g = w * 64u + (threadIdx.x & 63u);
     if (g >= total) return;
-    const int k = (int)(g / planec), ccol = (int)(g % planec);
-    const int I = ccol % nc, J = ccol / nc;
+    unsigned ccol;
+    int k;
+    storage_coords(g, w, planec, nz, ccol, k);
+    const int I = (int)(ccol % nc), J = (int)(ccol / nc);
     const size_t fs = (size_t)nz * F.plane, cs = (size_t)nz * planec;
     const double *cE = F.c, *cN = F.c + fs, *cU = F.c + 2 * fs;
-    const size_t o = (size_t)k * F.plane;
-    const int a = (2 * J) * n + 2 * I;  // child (2I, 2J)
-    const double e = 0.5 * (cE[o + a + 1] + cE[o + a + n + 1]);
-    const double nn = 0.5 * (cN[o + a + n] + cN[o + a + n + 1]);
-    const double u = 0.25 * (cU[o + a] + cU[o + a + 1] + cU[o + a + n] + cU[o + a + n + 1]);
+    auto at = [&](int i, int j) { return cell_index((size_t)j * n + i, k, F.plane, nz); };
+    const int i = 2 * I, j = 2 * J;  // child (2I, 2J)
+    const double e = 0.5 * (cE[at(i + 1, j)] + cE[at(i + 1, j + 1)]);
+    const double nn = 0.5 * (cN[at(i, j + 1)] + cN[at(i + 1, j + 1)]);
+    const double u = 0.25 * (cU[at(i, j)] + cU[at(i + 1, j)] + cU[at(i, j + 1)] + cU[at(i + 1, j + 1)]);
     cc[g] = e;
     cc[cs + g] = nn;
     cc[2 * cs + g] = u;
@@ -515,29 +525,43 @@ __global__ __launch_bounds__(256) void k_cast(const double *__restrict__ s, floa
         d[g] = (float)s[g];
 }
 
-// Input faces (either layout) -> level-major copy with the top U slot zeroed,
-// an FP32 copy when dst32 is given, and the count of real faces whose value
-// is not positive and finite added to *bad.
+// Input faces (either layout) -> tiled level-0 storage with the top U slot
+// zeroed, an FP32 copy when dst32 is given, and the count of real faces whose
+// value is not positive and finite added to *bad.  Thread = destination value.
 __global__ __launch_bounds__(256) void k_copy_coeffs(const double *__restrict__ src, int layout,
                                                      double *__restrict__ dst, float *__restrict__ dst32,
                                                      int plane, int nz, int *__restrict__ bad)
 {
-    const size_t per = (size_t)plane * nz;
-    const size_t total = 3 * per;
-    int cnt = 0;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
-        const int f = (int)(g / per);
-        const size_t r = g % per;
-        const int k = (int)(r / plane), col = (int)(r % plane);
-        double v = (layout == 0) ? src[g] : src[((size_t)col * nz + k) * 3 + f];
-        if (f == 2 && k == nz - 1)
-            v = 0.0;
-        else if (!(v > 0.0) || !(v <= kDblMax))
-            ++cnt;
-        dst[g] = v;
-        if (dst32) dst32[g] = (float)v;
+    const unsigned per = (unsigned)plane * nz;
+    const int f = blockIdx.y;
+    const unsigned w = storage_wave(), g = w * 64u + (threadIdx.x & 63u);
+    if (g >= per) return;
+    // level-major source: thread = source element (sequential reads);
+    // column-major source: thread = destination element
+    unsigned col;
+    int k;
+    size_t o = g;
+    double v;
+    if (layout == 0) {
+        v = src[(size_t)f * per + g];
+        if ((plane & 63) == 0) {
+            const unsigned cpb = (unsigned)plane >> 6, kk = w / cpb, tile = w - kk * cpb;
+            k = (int)kk;
+            o = ((size_t)tile * nz + kk) * 64 + (g & 63u);
+        } else {
+            k = (int)(g / (unsigned)plane);
+        }
+    } else {
+        storage_coords(g, w, plane, nz, col, k);
+        v = src[((size_t)col * nz + k) * 3 + f];
     }
-    if (cnt) atomicAdd(bad, cnt);
+    if (f == 2 && k == nz - 1)
+        v = 0.0;
+    else if (!(v > 0.0) || !(v <= kDblMax))
+        atomicAdd(bad, 1);
+    o += (size_t)f * per;
+    dst[o] = v;
+    if (dst32) dst32[o] = (float)v;
 }
 
 __global__ __launch_bounds__(256) void k_fill(double *__restrict__ x, double v, size_t n)
@@ -550,14 +574,18 @@ __global__ __launch_bounds__(256) void k_copy(double *__restrict__ d, const doub
     for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) d[g] = s[g];
 }
 
-// Tiled transpose of an R x C row-major matrix (element type E) through LDS.
+// Transposes of consecutive R x C row-major matrices (element type E)
+// through LDS, 32 x 32 blocks; the grid covers every block of every matrix.
 template <typename E>
 __global__ __launch_bounds__(256) void k_transpose(const E *__restrict__ src, E *__restrict__ dst,
                                                    int R, int C)
 {
     __shared__ E tile[32][33];
-    const int tiles_c = (C + 31) / 32;
-    const int bx = (int)(blockIdx.x % tiles_c) * 32, by = (int)(blockIdx.x / tiles_c) * 32;
+    const int tiles_c = (C + 31) / 32, tiles = tiles_c * ((R + 31) / 32);
+    const unsigned batch = blockIdx.x / tiles, t = blockIdx.x % tiles;
+    src += (size_t)batch * R * C;
+    dst += (size_t)batch * R * C;
+    const int bx = (int)(t % tiles_c) * 32, by = (int)(t / tiles_c) * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int yy = ty; yy < 32; yy += 8) {
         const int r = by + yy, c = bx + tx;
@@ -581,6 +609,38 @@ __global__ __launch_bounds__(256) void k_faces_to_column(const double *__restric
         const int k = (int)(r / plane), col = (int)(r % plane);
         dst[((size_t)col * nz + k) * 3 + f] = src[g];
     }
+}
+
+// Level-major [nz][plane] <-> tiled storage.  64 aligned columns of one level
+// are contiguous in both orders, so both sides are coalesced; the threads
+// follow the order of the source (sequential reads, 512-byte scattered
+// writes: 374 vs 530 us for 1 GiB on MI355X the other way round).
+template <typename E>
+__global__ __launch_bounds__(256) void k_level_to_tiled(const E *__restrict__ src, E *__restrict__ dst,
+                                                        E *__restrict__ dst2, int plane, int nz)
+{
+    const unsigned w = storage_wave(), g = w * 64u + (threadIdx.x & 63u);
+    if (g >= (unsigned)plane * nz) return;
+    const E v = src[g];
+    size_t o = g;  // plane not a multiple of 64: both orders agree
+    if ((plane & 63) == 0) {
+        const unsigned cpb = (unsigned)plane >> 6, k = w / cpb, tile = w - k * cpb;
+        o = ((size_t)tile * nz + k) * 64 + (g & 63u);
+    }
+    dst[o] = v;
+    if (dst2) dst2[o] = v;
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_tiled_to_level(const E *__restrict__ src, E *__restrict__ dst, int plane,
+                                                        int nz)
+{
+    const unsigned w = storage_wave(), g = w * 64u + (threadIdx.x & 63u);
+    if (g >= (unsigned)plane * nz) return;
+    unsigned col;
+    int k;
+    storage_coords(g, w, plane, nz, col, k);
+    dst[(size_t)k * plane + col] = src[g];
 }
 
 // ---- CG kernels (FP64) -----------------------------------------------------
@@ -607,7 +667,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     const Rsrc rp = make_rsrc(p_old, first ? 0 : n * 8);
     const Rsrc rpn = make_rsrc(p_new, n * 8), rq = make_rsrc(q, n * 8);
     const bool f32 = z32 != nullptr;
-    const unsigned zs = (unsigned)L.plane * (f32 ? 4u : 8u);
+    const unsigned zs = (unsigned)tile_width(L.plane) * (f32 ? 4u : 8u);
     const double beta = first ? 0.0 : sc->beta;
     // p_new at (k, lane offset o in bytes of a double)
     auto PV = [&](int k, unsigned o) -> double {
@@ -1009,8 +1069,8 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s)
 hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, float *dst32, int plane, int nz, int *bad,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy_coeffs, dim3(grid_for(3 * (size_t)plane * nz, 1)), dim3(256), 0, s, src, layout, dst,
-                       dst32, plane, nz, bad);
+    const unsigned blocks = (unsigned)(((size_t)plane * nz + 255) / 256);
+    hipLaunchKernelGGL(k_copy_coeffs, dim3(blocks, 3), dim3(256), 0, s, src, layout, dst, dst32, plane, nz, bad);
     return hipGetLastError();
 }
 
@@ -1026,13 +1086,53 @@ hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-static hipError_t transpose_elem(const void *src, void *dst, int R, int C, int elem, hipStream_t s)
+static hipError_t transpose_elem(const void *src, void *dst, int R, int C, int elem, hipStream_t s, int batches = 1)
 {
-    const dim3 grid((unsigned)(((C + 31) / 32) * (size_t)((R + 31) / 32)));
+    const dim3 grid((unsigned)(((C + 31) / 32) * (size_t)((R + 31) / 32) * batches));
     if (elem == 8)
         hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, s, (const double *)src, (double *)dst, R, C);
     else
         hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, (const float *)src, (float *)dst, R, C);
+    return hipGetLastError();
+}
+
+// Column-major [plane][nz] <-> tiled: each 64-column tile is a 64 x nz
+// transpose; a plane that is not a multiple of 64 is one plane x nz transpose.
+static hipError_t tile_transposes(const void *src, void *dst, int plane, int nz, int elem, bool to_tiled,
+                                  hipStream_t s)
+{
+    const int W = tile_width(plane), nt = plane / W;
+    return to_tiled ? transpose_elem(src, dst, W, nz, elem, s, nt) : transpose_elem(src, dst, nz, W, elem, s, nt);
+}
+
+hipError_t launch_cells_in(const void *src, int layout, void *dst, void *dst2, int plane, int nz, int elem,
+                           hipStream_t s)
+{
+    if (layout == 1) {
+        hipError_t e = tile_transposes(src, dst, plane, nz, elem, true, s);
+        if (e == hipSuccess && dst2) e = hipMemcpyAsync(dst2, dst, (size_t)plane * nz * elem, hipMemcpyDeviceToDevice, s);
+        return e;
+    }
+    const unsigned blocks = (unsigned)(((size_t)plane * nz + 255) / 256);
+    if (elem == 8)
+        hipLaunchKernelGGL(k_level_to_tiled<double>, dim3(blocks), dim3(256), 0, s, (const double *)src, (double *)dst,
+                           (double *)dst2, plane, nz);
+    else
+        hipLaunchKernelGGL(k_level_to_tiled<float>, dim3(blocks), dim3(256), 0, s, (const float *)src, (float *)dst,
+                           (float *)dst2, plane, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, int nz, int elem, hipStream_t s)
+{
+    if (layout == 1) return tile_transposes(src, dst, plane, nz, elem, false, s);
+    const unsigned blocks = (unsigned)(((size_t)plane * nz + 255) / 256);
+    if (elem == 8)
+        hipLaunchKernelGGL(k_tiled_to_level<double>, dim3(blocks), dim3(256), 0, s, (const double *)src, (double *)dst,
+                           plane, nz);
+    else
+        hipLaunchKernelGGL(k_tiled_to_level<float>, dim3(blocks), dim3(256), 0, s, (const float *)src, (float *)dst,
+                           plane, nz);
     return hipGetLastError();
 }
 

@@ -4,7 +4,9 @@
 // the lumped mass of Eq. LumpedMass) and the vector kernels of the outer
 // restarted GMRES (Sec. 5).
 //
-// Finest level only, FP64, level-major mixed vectors [uE | uN | uU | p]:
+// Finest level only, FP64, mixed vectors [uE | uN | uU | p] in the caller's
+// level-major order (the face coefficients and the V-cycle's vectors in the
+// level's tiled storage):
 // four blocks of m = n^2 nz values, face slot f of cell p joining p to its
 // east / north / upper neighbour, the U slot of the top cell unused (0).
 // With the face weights w_f of the pressure operator H = M3 + D W D^T:
@@ -25,12 +27,16 @@ namespace {
 
 constexpr int kMixedKC = 16;
 
-// Buffer descriptors of the four blocks of a mixed vector and of the three
-// face-coefficient arrays, with 32-bit byte offsets: column in the lane
-// offset, k plane in the wave-uniform offset (blocks hold < 2^32 bytes).
+// Buffer descriptors of the three face-coefficient arrays and 32-bit byte
+// offsets: column in the lane offset, k plane in the wave-uniform offset
+// (arrays hold < 2^32 bytes).  Mixed vectors are the caller's level-major
+// blocks (offsets v*, level stride vstride); the face coefficients and the
+// pressure-solve vectors use the level's tiled storage (offsets o*, stride
+// pstride).
 struct MixedRows {
     Rsrc cE, cN, cU;
     unsigned oc, oe, ow, on, os, pstride;
+    unsigned vc, ve, vw, vn, vs, vstride;
     __device__ MixedRows(const Level<double> &L, unsigned col)
     {
         const size_t m = (size_t)L.nz * L.plane;
@@ -38,12 +44,18 @@ struct MixedRows {
         cN = make_rsrc(L.c + m, m * 8);
         cU = make_rsrc(L.c + 2 * m, m * 8);
         const Nbr nb = neighbours(col, L.n, L.plane);
-        oc = col * 8u;
-        oe = nb.e * 8u;
-        ow = nb.w * 8u;
-        on = nb.n * 8u;
-        os = nb.s * 8u;
-        pstride = (unsigned)L.plane * 8u;
+        oc = cell_off(L, col);
+        oe = cell_off(L, nb.e);
+        ow = cell_off(L, nb.w);
+        on = cell_off(L, nb.n);
+        os = cell_off(L, nb.s);
+        pstride = (unsigned)tile_width(L.plane) * 8u;
+        vc = col * 8u;
+        ve = nb.e * 8u;
+        vw = nb.w * 8u;
+        vn = nb.n * 8u;
+        vs = nb.s * 8u;
+        vstride = (unsigned)L.plane * 8u;
     }
 };
 
@@ -63,54 +75,53 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_apply(Level<double> L,
                xP = make_rsrc(x + 3 * m, m * 8);
     const Rsrc yE = make_rsrc(y, m * 8), yN = make_rsrc(y + m, m * 8), yU = make_rsrc(y + 2 * m, m * 8),
                yP = make_rsrc(y + 3 * m, m * 8);
-    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;  // inactive lanes write nothing
+    const unsigned oo = active ? R.vc : 0xFFFFFFFFu;  // inactive lanes write nothing
     // vertical window: U face below the cell (weight, value), the cell's own
     // U face (weight, value) and the pressure of the cell
     double wUm = 0, xUm = 0;
     if (k0 > 0 && k0 - 1 < nz - 1) {
-        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
-        wUm = L.wz[k0 - 1] * ld(R.cU, R.oc, sm);
-        xUm = ld(xU, R.oc, sm);
+        wUm = L.wz[k0 - 1] * ld(R.cU, R.oc, (unsigned)(k0 - 1) * R.pstride);
+        xUm = ld(xU, R.vc, (unsigned)(k0 - 1) * R.vstride);
     }
 #pragma unroll
     for (int t = 0; t < kMixedKC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
-            const unsigned sk = (unsigned)k * R.pstride;
+            const unsigned sk = (unsigned)k * R.pstride, vk = (unsigned)k * R.vstride;
             const double h = L.wh[k];
-            const double xp = ld(xP, R.oc, sk);
+            const double xp = ld(xP, R.vc, vk);
             // east faces: own, west neighbour's, east neighbour's
             const double we = h * ld(R.cE, R.oc, sk), ww = h * ld(R.cE, R.ow, sk), wee = h * ld(R.cE, R.oe, sk);
-            const double xe = ld(xE, R.oc, sk), xw = ld(xE, R.ow, sk), xee = ld(xE, R.oe, sk);
-            const double ye = xe / we + 0.25 * (xw / sqrt(we * ww) + xee / sqrt(we * wee)) - (xp - ld(xP, R.oe, sk));
+            const double xe = ld(xE, R.vc, vk), xw = ld(xE, R.vw, vk), xee = ld(xE, R.ve, vk);
+            const double ye = xe / we + 0.25 * (xw / sqrt(we * ww) + xee / sqrt(we * wee)) - (xp - ld(xP, R.ve, vk));
             // north faces
             const double wn = h * ld(R.cN, R.oc, sk), ws = h * ld(R.cN, R.os, sk), wnn = h * ld(R.cN, R.on, sk);
-            const double xn = ld(xN, R.oc, sk), xs = ld(xN, R.os, sk), xnn = ld(xN, R.on, sk);
-            const double yn = xn / wn + 0.25 * (xs / sqrt(wn * ws) + xnn / sqrt(wn * wnn)) - (xp - ld(xP, R.on, sk));
+            const double xn = ld(xN, R.vc, vk), xs = ld(xN, R.vs, vk), xnn = ld(xN, R.vn, vk);
+            const double yn = xn / wn + 0.25 * (xs / sqrt(wn * ws) + xnn / sqrt(wn * wnn)) - (xp - ld(xP, R.vn, vk));
             // upper face (none above the top cell)
             double yu = 0, xu = 0, wu = 0;
             if (k + 1 < nz) {
-                const unsigned sp = sk + R.pstride;
+                const unsigned sp = sk + R.pstride, vp = vk + R.vstride;
                 wu = L.wz[k] * ld(R.cU, R.oc, sk);
-                xu = ld(xU, R.oc, sk);
+                xu = ld(xU, R.vc, vk);
                 double acc = xu / wu;
                 if (k >= 1) acc += 0.25 * xUm / sqrt(wu * wUm);
-                if (k + 2 < nz) acc += 0.25 * ld(xU, R.oc, sp) / sqrt(wu * (L.wz[k + 1] * ld(R.cU, R.oc, sp)));
-                yu = acc - (xp - ld(xP, R.oc, sp));
+                if (k + 2 < nz) acc += 0.25 * ld(xU, R.vc, vp) / sqrt(wu * (L.wz[k + 1] * ld(R.cU, R.oc, sp)));
+                yu = acc - (xp - ld(xP, R.vc, vp));
             }
             const double yp = (xe - xw) + (xn - xs) + (xu - xUm) + L.mu[k] * xp;
-            bstore(ye, yE, oo, sk);
-            bstore(yn, yN, oo, sk);
-            bstore(yu, yU, oo, sk);
-            bstore(yp, yP, oo, sk);
+            bstore(ye, yE, oo, vk);
+            bstore(yn, yN, oo, vk);
+            bstore(yu, yU, oo, vk);
+            bstore(yp, yP, oo, vk);
             wUm = wu;
             xUm = xu;
         }
     }
 }
 
-// t = r_p - D (W r_u); also fl32(t) when t32 is given.
-__global__ __launch_bounds__(kStreamThreads) void k_mixed_pre1(Level<double> L, const double *__restrict__ r,
+// t = a (r_p - D (W r_u)); also fl32(t) when t32 is given.
+__global__ __launch_bounds__(kStreamThreads) void k_mixed_pre1(Level<double> L, const double *__restrict__ r, double a,
                                                                double *__restrict__ t, float *__restrict__ t32)
 {
     int col, k0;
@@ -122,24 +133,24 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_pre1(Level<double> L, 
     const Rsrc rE = make_rsrc(r, m * 8), rN = make_rsrc(r + m, m * 8), rU = make_rsrc(r + 2 * m, m * 8),
                rP = make_rsrc(r + 3 * m, m * 8);
     const Rsrc rt = make_rsrc(t, m * 8), rt32 = make_rsrc(t32, t32 ? m * 4 : 0);
+    // t (tiled storage, the V-cycle's input)
     const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     const unsigned oo32 = active ? R.oc / 2 : 0xFFFFFFFFu;
     double fUm = 0;  // W r on the U face below
-    if (k0 > 0 && k0 - 1 < nz - 1) {
-        const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
-        fUm = L.wz[k0 - 1] * ld(R.cU, R.oc, sm) * ld(rU, R.oc, sm);
-    }
+    if (k0 > 0 && k0 - 1 < nz - 1)
+        fUm = L.wz[k0 - 1] * ld(R.cU, R.oc, (unsigned)(k0 - 1) * R.pstride) *
+              ld(rU, R.vc, (unsigned)(k0 - 1) * R.vstride);
 #pragma unroll
     for (int tt = 0; tt < kMixedKC; ++tt) {
         const int k = k0 + tt;
         if (k < nz) {
-            const unsigned sk = (unsigned)k * R.pstride;
+            const unsigned sk = (unsigned)k * R.pstride, vk = (unsigned)k * R.vstride;
             const double h = L.wh[k];
-            const double fU = (k + 1 < nz) ? L.wz[k] * ld(R.cU, R.oc, sk) * ld(rU, R.oc, sk) : 0.0;
-            const double div = (h * ld(R.cE, R.oc, sk) * ld(rE, R.oc, sk) - h * ld(R.cE, R.ow, sk) * ld(rE, R.ow, sk)) +
-                               (h * ld(R.cN, R.oc, sk) * ld(rN, R.oc, sk) - h * ld(R.cN, R.os, sk) * ld(rN, R.os, sk)) +
+            const double fU = (k + 1 < nz) ? L.wz[k] * ld(R.cU, R.oc, sk) * ld(rU, R.vc, vk) : 0.0;
+            const double div = (h * ld(R.cE, R.oc, sk) * ld(rE, R.vc, vk) - h * ld(R.cE, R.ow, sk) * ld(rE, R.vw, vk)) +
+                               (h * ld(R.cN, R.oc, sk) * ld(rN, R.vc, vk) - h * ld(R.cN, R.os, sk) * ld(rN, R.vs, vk)) +
                                (fU - fUm);
-            const double tv = ld(rP, R.oc, sk) - div;
+            const double tv = a * (ld(rP, R.vc, vk) - div);
             bstore(tv, rt, oo, sk);
             if (t32) bstore((float)tv, rt32, oo32, sk / 2);
             fUm = fU;
@@ -147,8 +158,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_pre1(Level<double> L, 
     }
 }
 
-// z_u = W (r_u + D^T y), z_p = y, with y in FP64 (y64) or FP32 (y32).
-__global__ __launch_bounds__(kStreamThreads) void k_mixed_pre2(Level<double> L, const double *__restrict__ r,
+// z_u = W (a r_u + D^T y), z_p = y, with y in FP64 (y64) or FP32 (y32).
+__global__ __launch_bounds__(kStreamThreads) void k_mixed_pre2(Level<double> L, const double *__restrict__ r, double a,
                                                                const double *__restrict__ y64,
                                                                const float *__restrict__ y32, double *__restrict__ z)
 {
@@ -161,27 +172,29 @@ __global__ __launch_bounds__(kStreamThreads) void k_mixed_pre2(Level<double> L, 
     const Rsrc rE = make_rsrc(r, m * 8), rN = make_rsrc(r + m, m * 8), rU = make_rsrc(r + 2 * m, m * 8);
     const Rsrc zE = make_rsrc(z, m * 8), zN = make_rsrc(z + m, m * 8), zU = make_rsrc(z + 2 * m, m * 8),
                zP = make_rsrc(z + 3 * m, m * 8);
+    // y: the V-cycle's output, tiled storage
     const bool f32 = y32 != nullptr;
     const Rsrc ry = f32 ? make_rsrc(y32, m * 4) : make_rsrc(y64, m * 8);
     auto Y = [&](unsigned voff, unsigned soff) -> double {
         return f32 ? (double)bload(float(), ry, voff / 2, soff / 2) : bload(double(), ry, voff, soff);
     };
-    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
+    const unsigned oo = active ? R.vc : 0xFFFFFFFFu;
 #pragma unroll
     for (int tt = 0; tt < kMixedKC; ++tt) {
         const int k = k0 + tt;
         if (k < nz) {
-            const unsigned sk = (unsigned)k * R.pstride;
+            const unsigned sk = (unsigned)k * R.pstride, vk = (unsigned)k * R.vstride;
             const double h = L.wh[k];
             const double yp = Y(R.oc, sk);
-            const double ze = h * ld(R.cE, R.oc, sk) * (ld(rE, R.oc, sk) + (yp - Y(R.oe, sk)));
-            const double zn = h * ld(R.cN, R.oc, sk) * (ld(rN, R.oc, sk) + (yp - Y(R.on, sk)));
-            const double zu =
-                (k + 1 < nz) ? L.wz[k] * ld(R.cU, R.oc, sk) * (ld(rU, R.oc, sk) + (yp - Y(R.oc, sk + R.pstride))) : 0.0;
-            bstore(ze, zE, oo, sk);
-            bstore(zn, zN, oo, sk);
-            bstore(zu, zU, oo, sk);
-            bstore(yp, zP, oo, sk);
+            const double ze = h * ld(R.cE, R.oc, sk) * (a * ld(rE, R.vc, vk) + (yp - Y(R.oe, sk)));
+            const double zn = h * ld(R.cN, R.oc, sk) * (a * ld(rN, R.vc, vk) + (yp - Y(R.on, sk)));
+            const double zu = (k + 1 < nz)
+                                  ? L.wz[k] * ld(R.cU, R.oc, sk) * (a * ld(rU, R.vc, vk) + (yp - Y(R.oc, sk + R.pstride)))
+                                  : 0.0;
+            bstore(ze, zE, oo, vk);
+            bstore(zn, zN, oo, vk);
+            bstore(zu, zU, oo, vk);
+            bstore(yp, zP, oo, vk);
         }
     }
 }
@@ -324,20 +337,20 @@ hipError_t launch_mixed_apply(const Level<double> &L, const double *x, double *y
     return hipGetLastError();
 }
 
-hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double *t, float *t32, hipStream_t s)
+hipError_t launch_mixed_pre1(const Level<double> &L, const double *r, double a, double *t, float *t32, hipStream_t s)
 {
     const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
     const int G = ncb * ((L.nz + kMixedKC - 1) / kMixedKC);
-    hipLaunchKernelGGL(k_mixed_pre1, dim3(G), dim3(kStreamThreads), 0, s, L, r, t, t32);
+    hipLaunchKernelGGL(k_mixed_pre1, dim3(G), dim3(kStreamThreads), 0, s, L, r, a, t, t32);
     return hipGetLastError();
 }
 
-hipError_t launch_mixed_pre2(const Level<double> &L, const double *r, const double *y64, const float *y32, double *z,
-                             hipStream_t s)
+hipError_t launch_mixed_pre2(const Level<double> &L, const double *r, double a, const double *y64, const float *y32,
+                             double *z, hipStream_t s)
 {
     const int ncb = (L.plane + kStreamThreads - 1) / kStreamThreads;
     const int G = ncb * ((L.nz + kMixedKC - 1) / kMixedKC);
-    hipLaunchKernelGGL(k_mixed_pre2, dim3(G), dim3(kStreamThreads), 0, s, L, r, y64, y32, z);
+    hipLaunchKernelGGL(k_mixed_pre2, dim3(G), dim3(kStreamThreads), 0, s, L, r, a, y64, y32, z);
     return hipGetLastError();
 }
 
