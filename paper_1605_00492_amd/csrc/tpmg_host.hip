@@ -114,7 +114,10 @@ tpmg_status validate_desc(const tpmg_desc *d)
             return fail(nullptr, TPMG_ERR_SHAPE, "coarsest level too large for the direct solve");
     }
     int M, CPW, P;
-    if (!sweep_shape(d->nz, false, &M, &CPW, &P) || !sweep_shape(d->nz, true, &M, &CPW, &P))
+    bool shape_ok = true;
+    for (int mode : {SWEEP_ZERO, SWEEP_GENERAL, SWEEP_PROLONG})
+        shape_ok = shape_ok && sweep_shape(d->nz, false, mode, &M, &CPW, &P) && sweep_shape(d->nz, true, mode, &M, &CPW, &P);
+    if (!shape_ok)
         return fail(nullptr, TPMG_ERR_SHAPE, "nz not supported");
     if (d->dz)
         for (int k = 0; k < d->nz; ++k)

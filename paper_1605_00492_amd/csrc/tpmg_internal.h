@@ -159,9 +159,9 @@ hipError_t launch_axpby(size_t n, double a, const double *x, double b, const dou
 // out[v] = fixed-order sum of the G partials of value v (v < nvals <= kMultiMax)
 hipError_t launch_sum_partials(const double *partials, int G, int nvals, double *stage, double *out, hipStream_t s);
 
-// Sweep chunking for a precision and column height: M cells per chunk, CPW
+// Sweep chunking for a precision, sweep mode and column height: M cells per chunk, CPW
 // chunks per wavefront, P wavefronts per 64-column tile; false if nz is not
 // supported.
-bool sweep_shape(int nz, bool fp32, int *M, int *CPW, int *P);
+bool sweep_shape(int nz, bool fp32, int mode, int *M, int *CPW, int *P);
 
 }  // namespace tpmg
