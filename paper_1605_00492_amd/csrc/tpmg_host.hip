@@ -53,7 +53,7 @@ struct tpmg_hierarchy {
     double *partials = nullptr;
     Scalars *sc = nullptr;
     int *bad = nullptr;
-    Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax + 1 doubles (dots_host)
+    Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax + 2 doubles (dots_host)
     double *dots_host = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -573,7 +573,7 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
         delete h;
         return code;
     };
-    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + (kMultiMax + 1) * sizeof(double), hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + (kMultiMax + 2) * sizeof(double), hipHostMallocDefault) !=
         hipSuccess)
         return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
     h->dots_host = reinterpret_cast<double *>(reinterpret_cast<char *>(h->sc_host) + sizeof(Scalars));
@@ -991,9 +991,9 @@ size_t plan_mixed(const tpmg_hierarchy *h, int restart, char *base, MixedWs *W)
     W->M = M;
     W->V = take((size_t)(restart + 1) * M * sizeof(double));
     W->Z = take((size_t)restart * M * sizeof(double));
-    W->partials = take((size_t)(kMultiMax + 1) * kMaxPartials * sizeof(double));
-    W->stage = take((size_t)(kMultiMax + 1) * kReduceSegs * sizeof(double));
-    W->out = take((size_t)(kMultiMax + 1) * sizeof(double));
+    W->partials = take((size_t)(kMultiMax + 2) * kMaxPartials * sizeof(double));
+    W->stage = take((size_t)(kMultiMax + 2) * kReduceSegs * sizeof(double));
+    W->out = take((size_t)(kMultiMax + 2) * sizeof(double));
     return (off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -1158,40 +1158,96 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
         g[0] = beta;
         int jj = 0;
         bool conv = false;
+        // Orthogonalisation: classical Gram-Schmidt, twice, with the second
+        // pass delayed.  The update of step j leaves the new vector u_{j+1}
+        // orthogonalised once and yields, in the same pass, its projections
+        // a_i onto the basis; a_i and rho_{j+1}^2 = |u|^2 - |a|^2 complete
+        // Hessenberg column j at once, and the correction
+        // q_{j+1} = (u_{j+1} - sum a_i q_i) / rho_{j+1} is applied in step
+        // j + 1's update pass (one pass over the basis per step).  Step j + 1
+        // preconditions u_{j+1} / rho_{j+1}: flexible GMRES only needs
+        // A z_j in the span of the basis.  When the projections are not small
+        // (|a|^2 > |u|^2 / 100) or the step has more than kMultiMax basis
+        // vectors, the second pass runs at once instead.
+        bool pend = false;  // slot j holds u_j, not yet corrected
+        double rho = 0.0;   // norm of the corrected u_j when pend
+        // aj: projections of u_{j+1} (then u_j) onto q_0 .. q_j; hv: of w
+        std::vector<double> aj(R + 1, 0.0), hv(R + 1, 0.0), ca(R + 1), cw(R + 1), sd(R + 1);
         for (int j = 0; j < R && it < opts->maxit; ++j) {
             double *zj = W.Z + (size_t)j * M;
             double *wj = W.V + (size_t)(j + 1) * M;  // becomes basis vector j + 1
+            double *uj = W.V + (size_t)j * M;        // (j >= 1) u_j, corrected in this step when pend
+            if (pend && j > kMultiMax) {
+                // too many basis vectors for the fused pass: correct u_j now
+                for (int i = 0; i < j; ++i) coef[i] = -aj[i] * sc[i];
+                if ((st = mixed_axpys(h, W, uj, vptr.data(), coef.data(), j, nullptr, s)) != TPMG_OK) return st;
+                sc[j] = 1.0 / rho;
+                pend = false;
+            }
             if ((st = mixed_precondition(h, vptr[j], sc[j], zj, fp32, s)) != TPMG_OK) return st;
             HIP_TRY(h, launch_mixed_apply(L0, zj, wj, s));
-            // classical Gram-Schmidt with selective reorthogonalisation: a
-            // second pass only when the first one cancels more than a factor
-            // 1/sqrt(2) of the norm of w (the "twice is enough" criterion)
             vptr[j + 1] = wj;  // (w, w) rides along with the first-pass dots
             if ((st = mixed_dots(h, W, wj, vptr.data(), j + 2, c.data(), s)) != TPMG_OK) return st;
             const double ww = c[j + 1];
-            double hn2 = 0.0;
-            for (int i = 0; i <= j; ++i) {
-                hcol[i] = c[i] * sc[i];
-                coef[i] = -hcol[i] * sc[i];
+            // projections of w onto q_0 .. q_j
+            for (int i = 0; i < j; ++i) hv[i] = c[i] * sc[i];
+            if (pend) {
+                double t = c[j];  // (u_j, w)
+                for (int i = 0; i < j; ++i) t -= aj[i] * hv[i];
+                hv[j] = t / rho;
+            } else {
+                hv[j] = c[j] * sc[j];
             }
-            if (j + 1 <= kMultiMax) {
-                // first update fused with the second pass's dots and the norm
+            double hn2 = 0.0;
+            bool done = false;  // u_{j+1} projections in aj[0..j], |u_{j+1}|^2 in hn2
+            if (pend) {
+                for (int i = 0; i < j; ++i) {
+                    ca[i] = aj[i] * sc[i] / rho;
+                    cw[i] = hv[i] * sc[i];
+                    sd[i] = sc[i];
+                }
+                HIP_TRY(h, launch_corr_axpy_dot(M, uj, wj, vptr.data(), ca.data(), cw.data(), sd.data(), j, 1.0 / rho,
+                                                hv[j], W.partials, W.stage, W.out, s));
+                HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(h, hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) aj[i] = h->dots_host[i];
+                hn2 = h->dots_host[j + 1];
+                sc[j] = 1.0;  // slot j now holds q_j
+                pend = false;
+                done = true;
+            } else if (j + 1 <= kMultiMax) {
+                for (int i = 0; i <= j; ++i) coef[i] = -hv[i] * sc[i];
                 HIP_TRY(h, launch_multiaxpy_dot(M, wj, vptr.data(), coef.data(), j + 1, W.partials, W.stage, W.out,
                                                 s));
                 HIP_TRY(h, hipMemcpyAsync(h->dots_host, W.out, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
                 HIP_TRY(h, hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) c[i] = h->dots_host[i];
+                for (int i = 0; i <= j; ++i) aj[i] = h->dots_host[i] * sc[i];
                 hn2 = h->dots_host[j + 1];
-            } else if ((st = mixed_axpys(h, W, wj, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) {
-                return st;
+                done = true;
+            } else {
+                for (int i = 0; i <= j; ++i) coef[i] = -hv[i] * sc[i];
+                if ((st = mixed_axpys(h, W, wj, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) return st;
             }
-            if (!(hn2 > 0.5 * ww)) {
-                if (j + 1 > kMultiMax && (st = mixed_dots(h, W, wj, vptr.data(), j + 1, c.data(), s)) != TPMG_OK)
-                    return st;
+            for (int i = 0; i <= j; ++i) hcol[i] = hv[i];
+            double aa = 0.0;
+            if (done)
+                for (int i = 0; i <= j; ++i) aa += aj[i] * aj[i];
+            if (done && aa <= 0.01 * hn2) {
+                // delay the correction of u_{j+1} to the next step
+                for (int i = 0; i <= j; ++i) hcol[i] += aj[i];
+                hn2 = hn2 - aa;
+                pend = hn2 > 0.0;
+            } else if (!(hn2 > 0.5 * ww) || done) {
+                // second pass now: large projections after the fused pass,
+                // or (more than kMultiMax basis vectors) the selective
+                // criterion, a second pass only when the first one cancels
+                // more than a factor 1/sqrt(2) of the norm of w
+                if (!done && (st = mixed_dots(h, W, wj, vptr.data(), j + 1, aj.data(), s)) != TPMG_OK) return st;
+                if (!done)
+                    for (int i = 0; i <= j; ++i) aj[i] *= sc[i];
                 for (int i = 0; i <= j; ++i) {
-                    const double hi = c[i] * sc[i];
-                    hcol[i] += hi;
-                    coef[i] = -hi * sc[i];
+                    hcol[i] += aj[i];
+                    coef[i] = -aj[i] * sc[i];
                 }
                 if ((st = mixed_axpys(h, W, wj, vptr.data(), coef.data(), j + 1, &hn2, s)) != TPMG_OK) return st;
             }
@@ -1201,6 +1257,7 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
                 break;
             }
             sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+            rho = hn;
             for (int i = 0; i <= j; ++i) H[(size_t)i * R + j] = hcol[i];
             H[(size_t)(j + 1) * R + j] = hn;
             for (int i = 0; i < j; ++i) {

@@ -151,8 +151,14 @@ hipError_t launch_multidot(size_t n, const double *w, const double *const *v, in
 hipError_t launch_multiaxpy(size_t n, double *y, const double *const *v, const double *a, int nv,
                             double *norm_partials, int *nblocks_out, hipStream_t s);
 // y += sum a_i v_i, then out[i] = (y, v_i) for i < nv and out[nv] = (y, y)
-// (nv + 1 values: partials, stage and out hold kMultiMax + 1 of them)
+// (nv + 1 values: partials, stage and out hold kMultiMax + 2 of them)
 hipError_t launch_multiaxpy_dot(size_t n, double *y, const double *const *v, const double *a, int nv,
+                                double *partials, double *stage, double *out, hipStream_t s);
+// Delayed reorthogonalisation step: u <- q = u * inv_rho - sum ca_i v_i,
+// w <- w' = w - sum cw_i v_i - hq q, then out[i] = (sd_i v_i, w') for i < nv,
+// out[nv] = (q, w'), out[nv + 1] = (w', w') (nv + 2 <= kMultiMax + 2 values)
+hipError_t launch_corr_axpy_dot(size_t n, double *u, double *w, const double *const *v, const double *ca,
+                                const double *cw, const double *sd, int nv, double inv_rho, double hq,
                                 double *partials, double *stage, double *out, hipStream_t s);
 // y = a x + b z (z == nullptr: y = a x); y may alias z
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, const double *z, double *y, hipStream_t s);

@@ -266,6 +266,45 @@ __global__ __launch_bounds__(256) void k_multiaxpy_dot(size_t n, double *__restr
     block_partials<NV + 1>(acc, partials, gridDim.x, blockIdx.x);
 }
 
+// Delayed reorthogonalisation (one pass over the basis per Arnoldi step).
+// u holds the previous step's once-orthogonalised vector; it is corrected
+// and normalised here, q = u / rho - sum_i ca_i v_i, while the new vector is
+// orthogonalised against the corrected basis, w' = w - sum_i cw_i v_i - hq q,
+// and the block parts of (sd_i v_i, w'), i < NV, (q, w') and (w', w') are
+// formed for the next step's correction.  u <- q and w <- w' in place.
+struct CorrSet {
+    const double *v[kMultiMax];
+    double ca[kMultiMax], cw[kMultiMax], sd[kMultiMax];
+};
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_corr_axpy_dot(size_t n, double *__restrict__ u, double *__restrict__ w,
+                                                       CorrSet S, double inv_rho, double hq,
+                                                       double *__restrict__ partials)
+{
+    double acc[NV + 2];
+#pragma unroll
+    for (int i = 0; i < NV + 2; ++i) acc[i] = 0.0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        double v[NV];
+        double q = u[g] * inv_rho, y = w[g];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            v[i] = S.v[i][g];
+            q -= S.ca[i] * v[i];
+            y -= S.cw[i] * v[i];
+        }
+        y -= hq * q;
+        u[g] = q;
+        w[g] = y;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += S.sd[i] * v[i] * y;
+        acc[NV] += q * y;
+        acc[NV + 1] += y * y;
+    }
+    block_partials<NV + 2>(acc, partials, gridDim.x, blockIdx.x);
+}
+
 // y = a x + b z (z may be null: y = a x).
 __global__ __launch_bounds__(256) void k_axpby(size_t n, double a, const double *__restrict__ x, double b,
                                                const double *__restrict__ z, double *__restrict__ y)
@@ -308,6 +347,13 @@ template <int NV>
 void launch_multiaxpy_dot_n(size_t n, double *y, const VecSet &S, double *partials, int G, hipStream_t s)
 {
     hipLaunchKernelGGL((k_multiaxpy_dot<NV>), dim3(G), dim3(256), 0, s, n, y, S, partials);
+}
+
+template <int NV>
+void launch_corr_n(size_t n, double *u, double *w, const CorrSet &S, double inv_rho, double hq, double *partials,
+                   int G, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_corr_axpy_dot<NV>), dim3(G), dim3(256), 0, s, n, u, w, S, inv_rho, hq, partials);
 }
 
 // Calls f(std::integral_constant<int, NV>) for 1 <= nv <= kMultiMax.
@@ -392,6 +438,23 @@ hipError_t launch_multiaxpy_dot(size_t n, double *y, const double *const *v, con
     const int G = vec_grid(n);
     dispatch_nv(nv, [&](auto NVc) { launch_multiaxpy_dot_n<decltype(NVc)::value>(n, y, S, partials, G, s); });
     return launch_sum_partials(partials, G, nv + 1, stage, out, s);
+}
+
+hipError_t launch_corr_axpy_dot(size_t n, double *u, double *w, const double *const *v, const double *ca,
+                                const double *cw, const double *sd, int nv, double inv_rho, double hq,
+                                double *partials, double *stage, double *out, hipStream_t s)
+{
+    if (nv < 1 || nv > kMultiMax) return hipErrorInvalidValue;
+    CorrSet S{};
+    for (int i = 0; i < nv; ++i) {
+        S.v[i] = v[i];
+        S.ca[i] = ca[i];
+        S.cw[i] = cw[i];
+        S.sd[i] = sd[i];
+    }
+    const int G = vec_grid(n);
+    dispatch_nv(nv, [&](auto NVc) { launch_corr_n<decltype(NVc)::value>(n, u, w, S, inv_rho, hq, partials, G, s); });
+    return launch_sum_partials(partials, G, nv + 2, stage, out, s);
 }
 
 hipError_t launch_axpby(size_t n, double a, const double *x, double b, const double *z, double *y, hipStream_t s)
