@@ -251,9 +251,13 @@ tpmg_status tpmg_destroy(tpmg_hierarchy *h);
  * tpmg_mixed_solve: restarted flexible GMRES (right preconditioning with
  *   P^{-1}, the V-cycle in the hierarchy's precision; Sec. 5 uses GMRES(30))
  *   from x = 0 until the Arnoldi residual estimate is <= rtol ||b||.
- *   Orthogonalisation: classical Gram-Schmidt, repeated when the first pass
- *   cancels more than a factor 1/sqrt(2) of the norm; fixed-order reductions.
- *   The Krylov vectors are kept unnormalised with their scales on the host.
+ *   Orthogonalisation: classical Gram-Schmidt twice, the second pass of each
+ *   vector delayed into the next step's update (one pass over the basis per
+ *   step); an immediate second pass when the first leaves projections above
+ *   a tenth of the norm, and beyond 16 basis vectors (there selectively, when
+ *   the first pass cancels more than a factor 1/sqrt(2) of the norm);
+ *   fixed-order reductions.  Krylov vectors are kept unnormalised with their
+ *   scales on the host.
  *   workspace: caller-owned device memory of at least
  *   tpmg_mixed_workspace_bytes(restart) bytes (2 restart + 1 mixed vectors
  *   plus reduction buffers), 256-byte aligned (TPMG_ERR_WORKSPACE otherwise).
