@@ -173,7 +173,9 @@ tpmg_status tpmg_face_gradient(const tpmg_hierarchy *h, const double *lambda_dev
 
 /*
  * Components of the V-cycle, exposed for testing and composition; level-major
- * buffers of the hierarchy's precision selected by fp32.
+ * buffers of the hierarchy's precision selected by fp32, staged through the
+ * hierarchy's CG vectors (so these calls must not overlap a solve on the
+ * same handle).
  *
  * tpmg_smooth: one damped line-relaxation sweep on a level (Sec. 4.2),
  *   u_out = u + omega H_z^{-1}(b - H u); u = NULL means u = 0.
