@@ -724,22 +724,30 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     const Level<double> L0 = level_view<double>(h, 0);
     const int flex = opts->flexible;
 
-    // b and x in the level's storage order (stage0, stage1); with a zero
-    // initial guess the conversion of b also writes r = b.
+    // b and x in the level's storage order (stage0, stage1)
     double *b = h->stage0, *x = h->stage1;
-    HIP_TRY(h, launch_cells_in(b_dev, layout, b, opts->x0_nonzero ? nullptr : h->r, plane, h->nz, 8, s));
-    if (opts->x0_nonzero) HIP_TRY(h, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, 8, s));
     HIP_TRY(h, launch_fill((double *)h->sc, 0.0, sizeof(Scalars) / sizeof(double), s));
     int G = 0;
+    bool r32_ready = false;  // fl32(r) already written
     if (opts->x0_nonzero) {
+        HIP_TRY(h, launch_cells_in(b_dev, layout, b, nullptr, plane, h->nz, 8, s));
+        HIP_TRY(h, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, 8, s));
         HIP_TRY(h, launch_residual(L0, x, b, h->r, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
         HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
     } else {
-        // r = b: one dot gives both (b, b) and (r, r)
-        HIP_TRY(h, launch_fill(x, 0.0, n, s));
-        HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+        // r = b: one reduction gives both (b, b) and (r, r)
+        if (layout == TPMG_LAYOUT_LEVEL_MAJOR) {
+            // one pass: b, r, fl32(r) in storage order, x = 0, (b, b)
+            HIP_TRY(h, launch_solve_start(b_dev, b, h->r, h->mixed ? h->r32 : nullptr, x, plane, h->nz, h->partials,
+                                          &G, s));
+            r32_ready = h->mixed;
+        } else {
+            HIP_TRY(h, launch_cells_in(b_dev, layout, b, h->r, plane, h->nz, 8, s));
+            HIP_TRY(h, launch_fill(x, 0.0, n, s));
+            HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+        }
         if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
         if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
     }
@@ -759,7 +767,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         converged = true;
         result = TPMG_OK;
     } else {
-        if (h->mixed) HIP_TRY(h, launch_cast(h->r, h->r32, n, s));
+        if (h->mixed && !r32_ready) HIP_TRY(h, launch_cast(h->r, h->r32, n, s));
         if ((st = precondition(h, s)) != TPMG_OK) return st;
         HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_RZ_FIRST, flex, s)) != TPMG_OK) return st;

@@ -108,6 +108,10 @@ hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
 hipError_t launch_cells_in(const void *src, int layout, void *dst, void *dst2, int plane, int nz, int elem,
                            hipStream_t s);
 hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, int nz, int elem, hipStream_t s);
+// Solve start from x = 0 with a level-major b: b, r = b (and fl32(r) into
+// r32 when given) in tiled storage, x = 0, partial sums of (b, b).
+hipError_t launch_solve_start(const double *bsrc, double *b, double *r, float *r32, double *x, int plane, int nz,
+                              double *partials, int *nblocks_out, hipStream_t s);
 // level-major <-> column-major cell transposes (elem = 4 or 8 bytes)
 hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, int elem,
                                  hipStream_t s);

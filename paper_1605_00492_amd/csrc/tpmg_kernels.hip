@@ -715,6 +715,35 @@ __global__ __launch_bounds__(256) void k_tiled_to_level(const E *__restrict__ sr
     dst[(size_t)k * plane + col] = src[g];
 }
 
+// Start of a solve from x = 0 with the caller's level-major b: b and r = b
+// in tiled storage (and fl32(r) when r32 is given), x = 0, and partial sums
+// of (b, b).  Threads follow the source order, four or more elements each.
+__global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ bsrc, double *__restrict__ b,
+                                                     double *__restrict__ r, float *__restrict__ r32,
+                                                     double *__restrict__ x, int plane, int nz,
+                                                     double *__restrict__ partials)
+{
+    const size_t total = (size_t)plane * nz;
+    const unsigned cpb = (unsigned)plane >> 6;
+    double acc = 0.0;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (size_t)gridDim.x * 256) {
+        const double v = bsrc[g];
+        size_t o = g;  // plane not a multiple of 64: both orders agree
+        if ((plane & 63) == 0) {
+            const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((unsigned)(g >> 6));
+            const unsigned k = w / cpb, tile = w - k * cpb;
+            o = ((size_t)tile * nz + k) * 64 + (g & 63);
+        }
+        b[o] = v;
+        r[o] = v;
+        if (r32) r32[o] = (float)v;
+        x[o] = 0.0;
+        acc += v * v;
+    }
+    double vv[1] = {acc};
+    block_partials<1>(vv, partials, gridDim.x, blockIdx.x);
+}
+
 // ---- CG kernels (FP64) -----------------------------------------------------
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = H p_new, and
@@ -1218,6 +1247,15 @@ hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, i
     else
         hipLaunchKernelGGL(k_tiled_to_level<float>, dim3(blocks), dim3(256), 0, s, (const float *)src, (float *)dst,
                            plane, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_start(const double *bsrc, double *b, double *r, float *r32, double *x, int plane, int nz,
+                              double *partials, int *nblocks_out, hipStream_t s)
+{
+    const int G = grid_for((size_t)plane * nz);
+    *nblocks_out = G;
+    hipLaunchKernelGGL(k_solve_start, dim3(G), dim3(256), 0, s, bsrc, b, r, r32, x, plane, nz, partials);
     return hipGetLastError();
 }
 
