@@ -24,6 +24,8 @@ WORKLOADS = {
     "graded_128x128x64": syn.scaled(syn.CONFIGS["fp64_512x512x64"], 128, levels=4),
     "adjoint_256x256x32": syn.CONFIGS["adjoint_256x256x32"],
     "ragged_48x48x13": syn.Workload("ragged_48x48x13", 48, 13, 4, 1.0, 1e3, True, "uniform"),
+    # n*n not a multiple of 64: every level stored level-major, a partial last tile
+    "untiled_20x20x9": syn.Workload("untiled_20x20x9", 20, 9, 3, 1.0, 1e3, True, "uniform"),
     # single-level line-Jacobi preconditioner (two sweeps) at nu_CFL = 8
     "single_level_64x64x16": syn.Workload("single_level_64x64x16", 64, 16, 1, 16.0, 1e4, True, "uniform",
                                           coarse="smooth", n_coarse=2),
