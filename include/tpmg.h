@@ -115,7 +115,10 @@ typedef struct {
 
 typedef struct tpmg_hierarchy tpmg_hierarchy;
 
-/* Workspace size for a description (validates it: SHAPE / INVALID_ARG / NOT_SPD for dz). */
+/* Workspace size for a description (validates it: SHAPE / INVALID_ARG / NOT_SPD for dz).
+ * TPMG_ERR_SHAPE also for grids whose FP64 level arrays would reach 4 GiB
+ * (n*n*nz >= 2^29; kernels use 32-bit byte offsets) or whose reductions would
+ * exceed the partial-sum buffer (about 4.8e8 cells). */
 tpmg_status tpmg_workspace_bytes(const tpmg_desc *desc, size_t *bytes);
 
 /*

@@ -93,8 +93,9 @@ tpmg_status validate_desc(const tpmg_desc *d)
     if (d->n % (1 << (d->nlevels - 1)) != 0)
         return fail(nullptr, TPMG_ERR_SHAPE, "n must be divisible by 2^(nlevels-1)");
     const double dof = (double)d->n * d->n * d->nz;
-    // reductions use one partial per workgroup of 256 columns x (4 to 16) cells
-    if (dof / (256.0 * 4.0) > (double)kMaxPartials * 0.9 || dof > 2.0e9)
+    // reductions use one partial per workgroup of 256 columns x (4 to 16)
+    // cells; kernels address each FP64 level array with 32-bit byte offsets
+    if (dof / (256.0 * 4.0) > (double)kMaxPartials * 0.9 || dof * 8.0 >= 4294967296.0)
         return fail(nullptr, TPMG_ERR_SHAPE, "grid too large");
     if (!(d->a_h >= 0.0) || !(d->a_z >= 0.0) || !std::isfinite(d->a_h) || !std::isfinite(d->a_z))
         return fail(nullptr, TPMG_ERR_INVALID_ARG, "a_h and a_z must be finite and >= 0");
