@@ -55,11 +55,18 @@ def desc(tp, **kw):
     (dict(a_z=-1.0), -1),
     (dict(coarse="smooth", n_coarse=0), -1),
     (dict(n=64, levels=2), -2),             # direct coarse level too large (32*32*16)
+    (dict(n=4096, nz=32, levels=9, coarse="smooth"), -2),   # 2^29 cells: FP64 arrays of 4 GiB
 ])
 def test_workspace_bytes_validation(tp, kw, status):
     with pytest.raises(tp.TpmgError) as ei:
         tp.workspace_bytes(desc(tp, **kw))
     assert ei.value.status == status
+
+
+def test_largest_grids_accepted(tp):
+    """Just below the 4 GiB-per-array limit the description is valid."""
+    n = tp.workspace_bytes(desc(tp, n=2048, nz=96, levels=8, coarse="smooth"))
+    assert n > 3 * 2048 * 2048 * 96 * 8
 
 
 def test_non_positive_spacing_is_not_spd(tp):
