@@ -93,9 +93,12 @@ void oracle_destroy(oracle_problem *P)
  * the fine faces covering the coarse face.
  *
  * The graded-spacing scaling (s_k, t_{k+1/2}) and the face-mean coarsening
- * are readings of a paper that treats constant coefficients and no grading:
- * parity unpinned against the paper beyond the uniform limit (closed-form
- * spectrum) and the exact Galerkin relation of the coarse operators.
+ * are readings of a paper that treats constant coefficients and no grading.
+ * The scaling is pinned by finite-volume identities (exact fluxes of linear
+ * profiles, horizontal Fourier modes on graded columns); the face-mean
+ * coarsening is parity unpinned against the paper beyond the uniform limit
+ * (closed-form spectrum) and the exact Galerkin relation of the coarse
+ * operators.
  *
  * Inputs: cE, cN, cU in column-contiguous order for level 0; dz may be NULL
  * (uniform).  Returns NULL on invalid input.

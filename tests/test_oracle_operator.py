@@ -127,3 +127,50 @@ def test_workload_generator_shapes():
     faces = w4.fd_faces(32)
     assert len(faces) == 32 and len({tuple(f) for f in faces}) == 32
     assert all(not (f == 2 and k == w4.nz - 1) for f, k, _, _ in faces)
+
+
+def _graded_grid(nz):
+    """An irregular graded column: cell widths s_k (mean 1) and centres z_k."""
+    dz = 1.05 ** np.arange(nz) * (1.0 + 0.3 * np.sin(np.arange(nz)))
+    s = dz / dz.mean()
+    return dz, s, np.cumsum(s) - 0.5 * s
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_graded_scaling_exact_for_linear_profiles(level):
+    """Finite-volume reading of the graded scaling (Sec. 4.2, Eq. Preconditioner
+    on cells of height s_k): the mass is the cell volume 4^l s_k and the vertical
+    flux through a face is a_z 4^l (p_{k+1} - p_k) / (distance between the
+    centres), which is exact for a linear profile p = z.  So H z = 4^l s_k z_k
+    in interior cells, and only the missing bottom / top faces leave a flux
+    imbalance of -/+ 4^l a_z.  A wrong mass scaling or a face distance other
+    than (s_k + s_{k+1}) / 2 breaks this identity."""
+    nz, n, a_h, a_z = 12, 8, 2.5, 40.0
+    dz, s, zc = _graded_grid(nz)
+    P = oracle.Problem(np.ones((3, nz, n, n)), a_h=a_h, a_z=a_z, dz=dz, levels=3)
+    nl = n >> level
+    x = np.broadcast_to(zc[:, None, None], (nz, nl, nl)).copy()
+    y = P.apply(x, level=level)
+    f = 4.0 ** level
+    expect = f * s * zc
+    expect[0] -= f * a_z
+    expect[-1] += f * a_z
+    np.testing.assert_allclose(y, np.broadcast_to(expect[:, None, None], y.shape), rtol=0, atol=1e-13 * f * a_z)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_graded_scaling_horizontal_mode(level):
+    """Horizontal faces of a graded cell have area proportional to s_k, so a
+    horizontal Fourier mode cos(2 pi i / n_l), constant in j and k, is an
+    eigenvector with eigenvalue s_k (4^l + 2 a_h (1 - cos(2 pi / n_l))) on every
+    level (coefficients 1; the coarse ones are means of ones)."""
+    nz, n, a_h, a_z = 12, 8, 2.5, 40.0
+    dz, s, _ = _graded_grid(nz)
+    P = oracle.Problem(np.ones((3, nz, n, n)), a_h=a_h, a_z=a_z, dz=dz, levels=3)
+    nl = n >> level
+    th = 2.0 * np.pi / nl
+    x = np.broadcast_to(np.cos(th * np.arange(nl))[None, None, :], (nz, nl, nl)).copy()
+    y = P.apply(x, level=level)
+    lam = s * (4.0 ** level + 2.0 * a_h * (1.0 - np.cos(th)))
+    np.testing.assert_allclose(y, lam[:, None, None] * x, rtol=0, atol=1e-13 * lam.max())
+
