@@ -197,8 +197,11 @@ __device__ __forceinline__ int sweep_tile(int t, int n, int bi, int bj)
     return j * TR + it;
 }
 
+// The FP32 prolongation sweep with 8-cell chunks needs 68 VGPRs unbounded;
+// held to 64 (eight wavefronts per SIMD, two 1024-thread workgroups per CU,
+// 16 bytes of spill) it runs 0.86 instead of 1.11 ms at 1024^2 x 128.
 template <typename T, int M, int CPW, int MODE, int LB>
-__global__ __launch_bounds__(LB) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
+__global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1) ? 8 : 1) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ ec, T omega,
                                               int tbi, int tbj)
 {
@@ -1078,11 +1081,11 @@ bool sweep_shape(int nz, bool fp32, int mode, int *M, int *CPW, int *P)
     static const int fm = env_int("TPMG_SWEEP_M"), fc = env_int("TPMG_SWEEP_CPW");
     int c = (fc == 1 || fc == 2) ? fc : 1;
     // Chunk length measured on 1024^2 x 128 (tiled storage): 8 cells (16
-    // wavefronts) for the FP32 zero-guess and general sweeps (general 0.66
-    // vs 0.70 ms) and the FP64 prolongation sweep (2.19 vs 2.22 ms); 16
-    // cells (8 wavefronts) for the others (FP32 prolongation 0.95 vs
-    // 1.11 ms, FP64 general 1.57 vs 1.70 ms).
-    const bool eight = fp32 ? mode != SWEEP_PROLONG : mode == SWEEP_PROLONG;
+    // wavefronts) for every FP32 sweep (general 0.66 vs 0.70 ms; the
+    // prolongation sweep, held to 64 VGPRs so that two workgroups share a CU,
+    // 0.86 vs 0.95 ms) and the FP64 prolongation sweep (2.19 vs 2.22 ms); 16
+    // cells (8 wavefronts) for the other FP64 sweeps (general 1.57 vs 1.70 ms).
+    const bool eight = fp32 || mode == SWEEP_PROLONG;
     int m = (fm == 4 || fm == 8 || fm == 16) ? fm : ((eight && (nz + 7) / 8 <= 16) ? 8 : 16);
     if (m == 16) c = 1;  // (16, 2) is not instantiated: too many registers
     // short columns: the smallest chunk that still covers them
