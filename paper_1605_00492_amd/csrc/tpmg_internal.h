@@ -101,7 +101,6 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_coeffs(const double *src, int layout, double *dst, float *dst32, int plane, int nz, int *bad,
                               hipStream_t s);
 hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s);
-hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s);
 // Caller's cells (layout 0 level-major, 1 column-major; elem = 4 or 8 bytes)
 // <-> the tiled storage of a level with this plane; cells_in also writes a
 // second copy to dst2 when given.
@@ -112,11 +111,9 @@ hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, i
 // r32 when given) in tiled storage, x = 0, partial sums of (b, b).
 hipError_t launch_solve_start(const double *bsrc, double *b, double *r, float *r32, double *x, int plane, int nz,
                               double *partials, int *nblocks_out, hipStream_t s);
-// level-major <-> column-major cell transposes (elem = 4 or 8 bytes)
+// column-major -> level-major cell transpose (elem = 4 or 8 bytes)
 hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, int elem,
                                  hipStream_t s);
-hipError_t launch_cells_to_column(const void *src, void *dst, int plane, int nz, int elem,
-                                  hipStream_t s);
 hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int nz,
                                   hipStream_t s);
 

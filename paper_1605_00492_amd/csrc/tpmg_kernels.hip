@@ -644,10 +644,6 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ x, double v, 
     for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) x[g] = v;
 }
 
-__global__ __launch_bounds__(256) void k_copy(double *__restrict__ d, const double *__restrict__ s, size_t n)
-{
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) d[g] = s[g];
-}
 
 // Transposes of consecutive R x C row-major matrices (element type E)
 // through LDS, 32 x 32 blocks; the grid covers every block of every matrix.
@@ -1197,11 +1193,6 @@ hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_copy(double *dst, const double *src, size_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
-    return hipGetLastError();
-}
 
 static hipError_t transpose_elem(const void *src, void *dst, int R, int C, int elem, hipStream_t s, int batches = 1)
 {
@@ -1267,10 +1258,6 @@ hipError_t launch_cells_to_level(const void *src, void *dst, int plane, int nz, 
     return transpose_elem(src, dst, plane, nz, elem, s);  // [plane][nz] -> [nz][plane]
 }
 
-hipError_t launch_cells_to_column(const void *src, void *dst, int plane, int nz, int elem, hipStream_t s)
-{
-    return transpose_elem(src, dst, nz, plane, elem, s);  // [nz][plane] -> [plane][nz]
-}
 
 hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int nz, hipStream_t s)
 {
