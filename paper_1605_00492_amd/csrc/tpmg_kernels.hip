@@ -197,10 +197,32 @@ __device__ __forceinline__ int sweep_tile(int t, int n, int bi, int bj)
     return j * TR + it;
 }
 
-// The FP32 prolongation sweep with 8-cell chunks needs 68 VGPRs unbounded;
-// held to 64 (eight wavefronts per SIMD, two 1024-thread workgroups per CU,
-// 16 bytes of spill) it runs 0.86 instead of 1.11 ms at 1024^2 x 128.
-template <typename T, int M, int CPW, int MODE, int LB>
+// A cell offset split into a per-lane part (vector register) and a
+// wave-uniform part (scalar register, added to the k-plane offset).
+struct Off {
+    unsigned v, s;
+};
+
+// Per-lane part of the offset of coarse column ic in a row of a tiled level
+// whose rows are whole tiles.
+__device__ __forceinline__ unsigned row_lane_off(unsigned ic, int nz, unsigned S)
+{
+    return ((ic >> 6) * (unsigned)nz * 64u + (ic & 63u)) * S;
+}
+
+// ROWS: the rows are whole tiles (n % 64 == 0; for the prolongation sweep
+// also n / 2 % 64 == 0).  A wavefront then covers 64 columns of one row, so
+// its north / south (and parent) rows are wave-uniform offsets: the buffers
+// are addressed from the lowest of the rows involved, with the row part of
+// every offset in a scalar register and only the centre, east and west
+// columns per lane.  This keeps the FP32 prolongation sweep at 64 VGPRs
+// without spilling.
+//
+// The FP32 prolongation sweep with 8-cell chunks needs more than 64 VGPRs
+// with per-lane offsets for all five neighbours; held to 64 (eight
+// wavefronts per SIMD, two 1024-thread workgroups per CU) it runs 0.86
+// instead of 1.11 ms at 1024^2 x 128.
+template <typename T, int M, int CPW, int MODE, int LB, bool ROWS>
 __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1) ? 8 : 1) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ ec, T omega,
                                               int tbi, int tbj)
@@ -216,35 +238,76 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
     const int tile = sweep_tile(xcd_remap(blockIdx.x, gridDim.x), L.n, tbi, tbj);
     const int col = tile * 64 + lane;
     const int nz = L.nz, plane = L.plane;
-    const bool active = col < plane;
+    const bool active = ROWS || col < plane;
     const unsigned cc = active ? col : 0;
-    const Nbr nb = neighbours(cc, L.n, plane);
     const size_t fstride = (size_t)nz * plane;
-    const Rsrc rb = make_rsrc(b, fstride * S);
-    const Rsrc rE = make_rsrc(L.c, fstride * S);
-    const Rsrc rN = make_rsrc(L.c + fstride, fstride * S);
-    const Rsrc rU = make_rsrc(L.c + 2 * fstride, fstride * S);
-    const Rsrc ru = make_rsrc(u, MODE == SWEEP_ZERO ? 0 : fstride * S);
-    const unsigned oc = cell_off(L, cc), oe = cell_off(L, nb.e), ow = cell_off(L, nb.w), on = cell_off(L, nb.n),
-                   os = cell_off(L, nb.s);
     const unsigned pstride = (unsigned)tile_width(plane) * S;
-
-    // Prolongation: every u value read is u + e(parent) (injection).
     const int nc = L.n >> 1, planec = nc * nc;
-    const Rsrc re = make_rsrc(ec, MODE == SWEEP_PROLONG ? (size_t)nz * planec * S : 0);
     const unsigned cstride = (unsigned)tile_width(planec) * S;
-    unsigned pc = 0, pe = 0, pw = 0, pn = 0, ps = 0;
-    if (MODE == SWEEP_PROLONG) {
-        auto poff = [&](int q) { return (unsigned)cell_base(parent(q, L.n), planec, nz) * S; };
-        pc = poff(cc);
-        pe = poff(nb.e);
-        pw = poff(nb.w);
-        pn = poff(nb.n);
-        ps = poff(nb.s);
+
+    // Fine offsets C (centre), E, W, N, Sx and parent offsets PC .. PS;
+    // fine buffers start at byte fbase, the coarse one at cbase.
+    Off C, E, W, N, Sx, PC{0, 0}, PE{0, 0}, PW{0, 0}, PN{0, 0}, PS{0, 0};
+    size_t fbase = 0, cbase = 0;
+    if constexpr (ROWS) {
+        const int TR = L.n >> 6, j = tile / TR, ti = tile - j * TR;
+        const int jn = (j + 1 == L.n) ? 0 : j + 1, js = (j == 0) ? L.n - 1 : j - 1;
+        const int j0 = min(j, min(jn, js));
+        const unsigned rowb = (unsigned)TR * nz * 64u * S, tileb = (unsigned)nz * 64u * S;
+        fbase = (size_t)j0 * rowb;
+        const unsigned ov = (unsigned)ti * tileb + (unsigned)lane * S;
+        const unsigned oe = lane < 63 ? ov + S : (unsigned)(ti + 1 == TR ? 0 : ti + 1) * tileb;
+        const unsigned ow = lane > 0 ? ov - S : (unsigned)(ti == 0 ? TR - 1 : ti - 1) * tileb + 63u * S;
+        const unsigned sc = (unsigned)(j - j0) * rowb;
+        C = {ov, sc};
+        E = {oe, sc};
+        W = {ow, sc};
+        N = {ov, (unsigned)(jn - j0) * rowb};
+        Sx = {ov, (unsigned)(js - j0) * rowb};
+        if (MODE == SWEEP_PROLONG) {
+            const int jc = j >> 1, jcn = jn >> 1, jcs = js >> 1, jc0 = min(jc, min(jcn, jcs));
+            const unsigned rowc = (unsigned)(nc >> 6) * nz * 64u * S;
+            cbase = (size_t)jc0 * rowc;
+            const unsigned i = (unsigned)(ti * 64 + lane);
+            const unsigned ie = (i + 1 == (unsigned)L.n) ? 0u : i + 1, iw = (i == 0) ? (unsigned)L.n - 1 : i - 1;
+            const unsigned pv = row_lane_off(i >> 1, nz, S), scc = (unsigned)(jc - jc0) * rowc;
+            PC = {pv, scc};
+            PE = {row_lane_off(ie >> 1, nz, S), scc};
+            PW = {row_lane_off(iw >> 1, nz, S), scc};
+            PN = {pv, (unsigned)(jcn - jc0) * rowc};
+            PS = {pv, (unsigned)(jcs - jc0) * rowc};
+        }
+    } else {
+        const Nbr nb = neighbours(cc, L.n, plane);
+        C = {cell_off(L, cc), 0u};
+        E = {cell_off(L, nb.e), 0u};
+        W = {cell_off(L, nb.w), 0u};
+        N = {cell_off(L, nb.n), 0u};
+        Sx = {cell_off(L, nb.s), 0u};
+        if (MODE == SWEEP_PROLONG) {
+            // Prolongation: every u value read is u + e(parent) (injection).
+            auto poff = [&](int q) { return Off{(unsigned)cell_base(parent(q, L.n), planec, nz) * S, 0u}; };
+            PC = poff(cc);
+            PE = poff(nb.e);
+            PW = poff(nb.w);
+            PN = poff(nb.n);
+            PS = poff(nb.s);
+        }
     }
-    auto U = [&](int k, unsigned o, unsigned po) -> T {
-        T v = bload(T(), ru, o, (unsigned)k * pstride);
-        if (MODE == SWEEP_PROLONG) v += bload(T(), re, po, (unsigned)k * cstride);
+    auto rs = [&](const T *a, size_t base, size_t bytes) {
+        return make_rsrc(reinterpret_cast<const char *>(a) + base, bytes - base);
+    };
+    const size_t fbytes = fstride * S;
+    const Rsrc rb = rs(b, fbase, fbytes);
+    const Rsrc rE = rs(L.c, fbase, fbytes);
+    const Rsrc rN = rs(L.c + fstride, fbase, fbytes);
+    const Rsrc rU = rs(L.c + 2 * fstride, fbase, fbytes);
+    const Rsrc ru = MODE == SWEEP_ZERO ? make_rsrc(u, 0) : rs(u, fbase, fbytes);
+    const Rsrc re = MODE == SWEEP_PROLONG ? rs(ec, cbase, (size_t)nz * planec * S) : make_rsrc(ec, 0);
+    auto ld = [&](const Rsrc &r, Off o, int k) -> T { return bload(T(), r, o.v, o.s + (unsigned)k * pstride); };
+    auto U = [&](int k, Off o, Off po) -> T {
+        T v = ld(ru, o, k);
+        if (MODE == SWEEP_PROLONG) v += bload(T(), re, po.v, po.s + (unsigned)k * cstride);
         return v;
     };
 
@@ -258,10 +321,10 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
         u_dn[c] = u_c[c] = wD[c] = T(0);
         if (k0[c] < nz) {
             if (k0[c] > 0) {
-                wD[c] = L.wz[k0[c] - 1] * bload(T(), rU, oc, (unsigned)(k0[c] - 1) * pstride);
-                if (MODE != SWEEP_ZERO) u_dn[c] = U(k0[c] - 1, oc, pc);
+                wD[c] = L.wz[k0[c] - 1] * ld(rU, C, k0[c] - 1);
+                if (MODE != SWEEP_ZERO) u_dn[c] = U(k0[c] - 1, C, PC);
             }
-            if (MODE != SWEEP_ZERO) u_c[c] = U(k0[c], oc, pc);
+            if (MODE != SWEEP_ZERO) u_c[c] = U(k0[c], C, PC);
         }
         cs[c].init();
     }
@@ -274,20 +337,19 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
         for (int c = 0; c < CPW; ++c) {
             const int k = k0[c] + t;
             if (k < nz) {
-                const unsigned sk = (unsigned)k * pstride;
-                R[c].b = bload(T(), rb, oc, sk);
-                R[c].cE = bload(T(), rE, oc, sk);
-                R[c].cEw = bload(T(), rE, ow, sk);
-                R[c].cN = bload(T(), rN, oc, sk);
-                R[c].cNs = bload(T(), rN, os, sk);
-                R[c].cU = bload(T(), rU, oc, sk);
+                R[c].b = ld(rb, C, k);
+                R[c].cE = ld(rE, C, k);
+                R[c].cEw = ld(rE, W, k);
+                R[c].cN = ld(rN, C, k);
+                R[c].cNs = ld(rN, Sx, k);
+                R[c].cU = ld(rU, C, k);
                 R[c].uup = R[c].uE = R[c].uW = R[c].uN = R[c].uS = T(0);
                 if (MODE != SWEEP_ZERO) {
-                    if (k + 1 < nz) R[c].uup = U(k + 1, oc, pc);
-                    R[c].uE = U(k, oe, pe);
-                    R[c].uW = U(k, ow, pw);
-                    R[c].uN = U(k, on, pn);
-                    R[c].uS = U(k, os, ps);
+                    if (k + 1 < nz) R[c].uup = U(k + 1, C, PC);
+                    R[c].uE = U(k, E, PE);
+                    R[c].uW = U(k, W, PW);
+                    R[c].uN = U(k, N, PN);
+                    R[c].uS = U(k, Sx, PS);
                 }
             }
         }
@@ -328,8 +390,8 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
     __syncthreads();
     if (p == 0) coupling_solve(red, Q, lane);
     __syncthreads();
-    const Rsrc ro = make_rsrc(out, fstride * S);
-    const unsigned oo = active ? oc : 0xFFFFFFFFu;  // inactive lanes write nothing
+    const Rsrc ro = rs(out, fbase, fbytes);
+    const unsigned oo = active ? C.v : 0xFFFFFFFFu;  // inactive lanes write nothing (C.s = 0 there)
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         const int q = c * P + p;
@@ -338,7 +400,7 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int k = k0[c] + t;
-            if (k < nz) bstore(su[c][t] + omega * cs[c].value(t, xlo, xhi), ro, oo, (unsigned)k * pstride);
+            if (k < nz) bstore(su[c][t] + omega * cs[c].value(t, xlo, xhi), ro, oo, C.s + (unsigned)k * pstride);
         }
     }
 }
@@ -1041,17 +1103,32 @@ hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, 
     const int tiles = (L.plane + 63) / 64;
     const dim3 block(64 * P);
     const size_t lds = (size_t)P * CPW * 512 * sizeof(T);
+    // Row-uniform neighbour offsets where the rows are whole tiles on this
+    // level (and, for the prolongation sweep, on the coarser one).  Measured
+    // on 1024^2 x 128 they help the FP32 prolongation sweep (0.80 vs 0.86 ms:
+    // 8 instead of 16 bytes of spill) and cost about 1 % elsewhere, so by
+    // default only that sweep uses them (TPMG_SWEEP_ROWS=1: every sweep that
+    // can, 0: none).
+    static const int erows = env_int("TPMG_SWEEP_ROWS");
+    const bool fits = L.n % 64 == 0 && (mode != SWEEP_PROLONG || L.n % 128 == 0);
+    const bool rows = fits && (erows == 1 || (erows < 0 && sizeof(T) == 4 && mode == SWEEP_PROLONG));
+    auto go = [&](auto mc, auto rc) {
+        hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value>), dim3(tiles), block, lds,
+                           s, L, u, b, out, ec, omega, tbi, tbj);
+    };
+    using RT = std::true_type;
+    using RF = std::false_type;
     switch (mode) {
     case SWEEP_ZERO:
-        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_ZERO, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
+        rows ? go(std::integral_constant<int, SWEEP_ZERO>(), RT()) : go(std::integral_constant<int, SWEEP_ZERO>(), RF());
         break;
     case SWEEP_GENERAL:
-        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_GENERAL, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec,
-                           omega, tbi, tbj);
+        rows ? go(std::integral_constant<int, SWEEP_GENERAL>(), RT())
+             : go(std::integral_constant<int, SWEEP_GENERAL>(), RF());
         break;
     default:
-        hipLaunchKernelGGL((k_sweep<T, M, CPW, SWEEP_PROLONG, LB>), dim3(tiles), block, lds, s, L, u, b, out, ec,
-                           omega, tbi, tbj);
+        rows ? go(std::integral_constant<int, SWEEP_PROLONG>(), RT())
+             : go(std::integral_constant<int, SWEEP_PROLONG>(), RF());
         break;
     }
     return hipGetLastError();

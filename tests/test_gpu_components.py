@@ -40,6 +40,10 @@ CASES = {
     "flat8x1": (8, 1, 2, 10.0, False, "smooth"),
     "deep64x128": (64, 128, 3, 1e4, True, "smooth"),
     "deep32x256": (32, 256, 2, 1e4, True, "smooth"),
+    # rows of whole 64-column tiles on level 0 and its parent level: the
+    # FP32 prolongation sweep's row-uniform addressing (two tiles per row,
+    # periodic wrap, a ragged last chunk)
+    "rows128x13": (128, 13, 3, 1e4, True, "smooth"),
 }
 
 TOL64_OP, TOL64, TOL32 = 1e-13, 1e-12, 2e-5
