@@ -158,7 +158,9 @@ tpmg_status tpmg_vcycle(const tpmg_hierarchy *h, int32_t fp32, const void *b_dev
  * outer iteration; FP32 V-cycle on fl32(r) in mixed hierarchies).  b, x: FP64,
  * n*n*nz values in `layout`.  Returns TPMG_OK, TPMG_NOT_CONVERGED (x holds the
  * last iterate), TPMG_ERR_BREAKDOWN, or an argument/device error.  info may be
- * NULL.  Synchronises `stream`.
+ * NULL; otherwise one more operator pass recomputes ||b - H x|| for
+ * info->true_rel_residual (and, in level-major layout, writes x on the way).
+ * Synchronises `stream`.
  */
 tpmg_status tpmg_solve(const tpmg_hierarchy *h, const double *b_dev, double *x_dev, int32_t layout,
                        const tpmg_solve_opts *opts, tpmg_solve_info *info, void *stream);

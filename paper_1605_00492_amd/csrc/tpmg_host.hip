@@ -733,7 +733,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     if (opts->x0_nonzero) {
         HIP_TRY(h, launch_cells_in(b_dev, layout, b, nullptr, plane, h->nz, 8, s));
         HIP_TRY(h, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, 8, s));
-        HIP_TRY(h, launch_residual(L0, x, b, h->r, h->partials, &G, s));
+        HIP_TRY(h, launch_residual(L0, x, b, h->r, nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
         HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
@@ -814,8 +814,12 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         }
         if (it > opts->maxit) it = opts->maxit;
     }
+    bool x_out = false;  // x already copied to x_dev
     if (info) {
-        HIP_TRY(h, launch_residual(L0, x, b, h->q, h->partials, &G, s));
+        // true residual norm; a level-major x_dev is written by the same pass
+        double *xo = layout == TPMG_LAYOUT_LEVEL_MAJOR ? x_dev : nullptr;
+        HIP_TRY(h, launch_residual(L0, x, b, nullptr, xo, h->partials, &G, s));
+        x_out = xo != nullptr;
         if ((st = finalize(h, G, 1, ST_TT, 0, s)) != TPMG_OK) return st;
         if ((st = read_scalars(h, s)) != TPMG_OK) return st;
         info->iterations = it;
@@ -823,7 +827,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         info->rel_residual = rel;
         info->true_rel_residual = bnorm > 0 ? std::sqrt(h->sc_host->tt) / bnorm : 0.0;
     }
-    HIP_TRY(h, launch_cells_out(x, x_dev, layout, plane, h->nz, 8, s));
+    if (!x_out) HIP_TRY(h, launch_cells_out(x, x_dev, layout, plane, h->nz, 8, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     return result;
 }

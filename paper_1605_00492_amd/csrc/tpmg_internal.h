@@ -128,7 +128,9 @@ hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, co
                              hipStream_t s);
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32,
                       double *partials, int *nblocks_out, hipStream_t s);
-hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
+// r = b - H x (r null: the norm only) and partial sums of (r, r); with xout
+// non-null, x is also copied there in level-major order.
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r, double *xout,
                            double *partials, int *nblocks_out, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage,
                            int flexible, double *stage_buf, hipStream_t s);

@@ -870,11 +870,14 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
-// r = b - H x, and partial sums of (r, r).
+// r = b - H x (r may be null: the norm only), and partial sums of (r, r).
+// With xout, x is also written there in level-major order (the end of a
+// solve: the copy of the iterate to the caller rides on this pass).
 template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, const double *__restrict__ x,
                                                              const double *__restrict__ b,
                                                              double *__restrict__ r,
+                                                             double *__restrict__ xout,
                                                              double *__restrict__ partials)
 {
     int col, k0;
@@ -883,8 +886,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
     const int nz = L.nz;
     const StencilRows<double> R(L, col);
     const size_t fbytes = (size_t)nz * L.plane * 8;
-    const Rsrc rx = make_rsrc(x, fbytes), rb = make_rsrc(b, fbytes), rr = make_rsrc(r, fbytes);
-    const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
+    const Rsrc rx = make_rsrc(x, fbytes), rb = make_rsrc(b, fbytes), rr = make_rsrc(r, r ? fbytes : 0);
+    const Rsrc rxo = make_rsrc(xout, xout ? fbytes : 0);
+    const unsigned oo = active ? R.oc : 0xFFFFFFFFu, ol = active ? (unsigned)col * 8u : 0xFFFFFFFFu;
+    const unsigned lstride = (unsigned)L.plane * 8u;
     double xm = 0, wD = 0;
     if (k0 > 0) {
         const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
@@ -907,7 +912,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
                               h * bload(double(), R.rN, R.os, sk) * (xc - bload(double(), rx, R.os, sk)) +
                               wU * (xc - xp) + wD * (xc - xm);
             const double rv = bload(double(), rb, R.oc, sk) - hx;
-            bstore(rv, rr, oo, sk);
+            if (r) bstore(rv, rr, oo, sk);
+            if (xout) bstore(xc, rxo, ol, (unsigned)k * lstride);
             if (active) acc += rv * rv;
             xm = xc;
             xc = xp;
@@ -1357,7 +1363,7 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     });
 }
 
-hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r,
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r, double *xout,
                            double *partials, int *nblocks_out, hipStream_t s)
 {
     const int kc = stream_kc(L.nz >= 64 && L.plane >= 256 * 256 ? 64 : 16);
@@ -1365,7 +1371,7 @@ hipError_t launch_residual(const Level<double> &L, const double *x, const double
     *nblocks_out = G;
     return with_kc(kc, [&](auto KCc) {
         hipLaunchKernelGGL((k_residual<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b, r,
-                           partials);
+                           xout, partials);
         return hipGetLastError();
     });
 }

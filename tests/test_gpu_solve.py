@@ -142,3 +142,32 @@ def test_solve_deterministic(work):
     x2, i2 = H.solve(bt, rtol=w.rtol)
     assert i1["iterations"] == i2["iterations"] and np.array_equal(host(x1), host(x2))
     H.close()
+
+
+def test_solve_without_info(work):
+    """The C entry point accepts info = NULL.  Then no true-residual pass
+    runs and the layout pass copies x to the caller; with info, a level-major
+    x is written by the true-residual pass instead.  Same iterate bit for bit,
+    in both layouts."""
+    import ctypes as C
+
+    from paper_1605_00492_amd import binding as B
+    w = work["w"]
+    if w.dof > 2_000_000:
+        pytest.skip("checked on the smaller workloads")
+    for precision, layout in (("fp64", "level"), ("mixed", "level"), ("fp64", "column")):
+        c, b = work["c"], work["b"]
+        if layout == "column":
+            c = np.ascontiguousarray(np.transpose(c, (2, 3, 1, 0)))
+            b = np.ascontiguousarray(np.transpose(b, (1, 2, 0)))
+        H = hier(w, c, precision=precision, layout=layout)
+        bt = to_dev(b)
+        x1, _ = H.solve(bt, rtol=w.rtol, maxit=100)
+        x2 = torch.full_like(bt, float("nan"))
+        opts = B.SolveOpts()
+        opts.rtol, opts.maxit, opts.x0_nonzero, opts.flexible, opts.history = w.rtol, 100, 0, int(H.mixed), None
+        st = B.lib().tpmg_solve(H.handle, B._ptr(bt), B._ptr(x2), H.layout, C.byref(opts), None,
+                                B._stream(H.device))
+        assert st == 0, (precision, layout, st)
+        assert np.array_equal(host(x1), host(x2)), (precision, layout)
+        H.close()
