@@ -730,20 +730,25 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     HIP_TRY(h, launch_fill((double *)h->sc, 0.0, sizeof(Scalars) / sizeof(double), s));
     int G = 0;
     bool r32_ready = false;  // fl32(r) already written
+    // Level-major start from x = 0: the tiled copy of b is not formed (the
+    // final residual reads the caller's b) and x is not zeroed: the first
+    // update writes x = alpha p, and x is zeroed only if no update runs.
+    bool b_level = false, x_unset = false;
     if (opts->x0_nonzero) {
         HIP_TRY(h, launch_cells_in(b_dev, layout, b, nullptr, plane, h->nz, 8, s));
         HIP_TRY(h, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, 8, s));
-        HIP_TRY(h, launch_residual(L0, x, b, h->r, nullptr, h->partials, &G, s));
+        HIP_TRY(h, launch_residual(L0, x, b, 0, h->r, nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
         HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
     } else {
         // r = b: one reduction gives both (b, b) and (r, r)
         if (layout == TPMG_LAYOUT_LEVEL_MAJOR) {
-            // one pass: b, r, fl32(r) in storage order, x = 0, (b, b)
-            HIP_TRY(h, launch_solve_start(b_dev, b, h->r, h->mixed ? h->r32 : nullptr, x, plane, h->nz, h->partials,
-                                          &G, s));
+            // one pass: r, fl32(r) in storage order, (b, b)
+            HIP_TRY(h, launch_solve_start(b_dev, nullptr, h->r, h->mixed ? h->r32 : nullptr, nullptr, plane, h->nz,
+                                          h->partials, &G, s));
             r32_ready = h->mixed;
+            b_level = x_unset = true;
         } else {
             HIP_TRY(h, launch_cells_in(b_dev, layout, b, h->r, plane, h->nz, 8, s));
             HIP_TRY(h, launch_fill(x, 0.0, n, s));
@@ -764,7 +769,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         result = TPMG_ERR_BREAKDOWN;
         fail(h, result, "non-finite right-hand side or initial residual");
     } else if (bnorm == 0.0 || rnorm <= opts->rtol * bnorm) {
-        if (bnorm == 0.0) HIP_TRY(h, launch_fill(x, 0.0, n, s));
+        if (bnorm == 0.0 && !x_unset) HIP_TRY(h, launch_fill(x, 0.0, n, s));
         converged = true;
         result = TPMG_OK;
     } else {
@@ -784,7 +789,9 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
                 Timed t(h, TPMG_K_PCG_UPDATE, s);
                 HIP_TRY(h, launch_pcg_update(n, x, pnew, h->r, h->q, h->mixed ? h->r32 : nullptr,
                                              (flex && !h->mixed) ? h->z : nullptr,
-                                             (flex && h->mixed) ? h->z32 : nullptr, h->sc, h->partials, &G, s));
+                                             (flex && h->mixed) ? h->z32 : nullptr, h->sc, h->partials,
+                                             x_unset ? 1 : 0, &G, s));
+                x_unset = false;
             }
             if ((st = finalize(h, G, 2, ST_RR_RZO, flex, s)) != TPMG_OK) return st;
             if ((st = read_scalars(h, s)) != TPMG_OK) return st;
@@ -814,11 +821,12 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         }
         if (it > opts->maxit) it = opts->maxit;
     }
+    if (x_unset) HIP_TRY(h, launch_fill(x, 0.0, n, s));  // no update ran
     bool x_out = false;  // x already copied to x_dev
     if (info) {
         // true residual norm; a level-major x_dev is written by the same pass
         double *xo = layout == TPMG_LAYOUT_LEVEL_MAJOR ? x_dev : nullptr;
-        HIP_TRY(h, launch_residual(L0, x, b, nullptr, xo, h->partials, &G, s));
+        HIP_TRY(h, launch_residual(L0, x, b_level ? b_dev : b, b_level ? 1 : 0, nullptr, xo, h->partials, &G, s));
         x_out = xo != nullptr;
         if ((st = finalize(h, G, 1, ST_TT, 0, s)) != TPMG_OK) return st;
         if ((st = read_scalars(h, s)) != TPMG_OK) return st;

@@ -107,8 +107,9 @@ hipError_t launch_fill(double *x, double v, size_t n, hipStream_t s);
 hipError_t launch_cells_in(const void *src, int layout, void *dst, void *dst2, int plane, int nz, int elem,
                            hipStream_t s);
 hipError_t launch_cells_out(const void *src, void *dst, int layout, int plane, int nz, int elem, hipStream_t s);
-// Solve start from x = 0 with a level-major b: b, r = b (and fl32(r) into
-// r32 when given) in tiled storage, x = 0, partial sums of (b, b).
+// Solve start from x = 0 with a level-major b: r = b (and fl32(r) into r32
+// when given) in tiled storage, b and x = 0 there when given (may be null),
+// partial sums of (b, b).
 hipError_t launch_solve_start(const double *bsrc, double *b, double *r, float *r32, double *x, int plane, int nz,
                               double *partials, int *nblocks_out, hipStream_t s);
 // column-major -> level-major cell transpose (elem = 4 or 8 bytes)
@@ -122,16 +123,18 @@ hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int
 hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32,
                             const double *p_old, double *p_new, double *q, const Scalars *sc,
                             int first, double *partials, int *nblocks_out, hipStream_t s);
+// x += alpha p (x = alpha p without reading x when x_first), r -= alpha q, ...
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q,
                              float *r32, const double *zold, const float *zold32,
-                             const Scalars *sc, double *partials, int *nblocks_out,
+                             const Scalars *sc, double *partials, int x_first, int *nblocks_out,
                              hipStream_t s);
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32,
                       double *partials, int *nblocks_out, hipStream_t s);
-// r = b - H x (r null: the norm only) and partial sums of (r, r); with xout
-// non-null, x is also copied there in level-major order.
-hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r, double *xout,
-                           double *partials, int *nblocks_out, hipStream_t s);
+// r = b - H x (r null: the norm only) and partial sums of (r, r); b in the
+// level's storage, or level-major with b_level; with xout non-null, x is also
+// copied there in level-major order.
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, int b_level, double *r,
+                           double *xout, double *partials, int *nblocks_out, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scalars *sc, int stage,
                            int flexible, double *stage_buf, hipStream_t s);
 hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x,

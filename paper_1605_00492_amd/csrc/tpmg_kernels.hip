@@ -776,9 +776,10 @@ __global__ __launch_bounds__(256) void k_tiled_to_level(const E *__restrict__ sr
     dst[(size_t)k * plane + col] = src[g];
 }
 
-// Start of a solve from x = 0 with the caller's level-major b: b and r = b
-// in tiled storage (and fl32(r) when r32 is given), x = 0, and partial sums
-// of (b, b).  Threads follow the source order, four or more elements each.
+// Start of a solve from x = 0 with the caller's level-major b: r = b in
+// tiled storage (and fl32(r) when r32 is given), b and x = 0 there when they
+// are given, and partial sums of (b, b).  Threads follow the source order,
+// four or more elements each.
 __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ bsrc, double *__restrict__ b,
                                                      double *__restrict__ r, float *__restrict__ r32,
                                                      double *__restrict__ x, int plane, int nz,
@@ -795,10 +796,10 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
             const unsigned k = w / cpb, tile = w - k * cpb;
             o = ((size_t)tile * nz + k) * 64 + (g & 63);
         }
-        b[o] = v;
+        if (b) b[o] = v;
         r[o] = v;
         if (r32) r32[o] = (float)v;
-        x[o] = 0.0;
+        if (x) x[o] = 0.0;
         acc += v * v;
     }
     double vv[1] = {acc};
@@ -871,11 +872,12 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
 }
 
 // r = b - H x (r may be null: the norm only), and partial sums of (r, r).
-// With xout, x is also written there in level-major order (the end of a
-// solve: the copy of the iterate to the caller rides on this pass).
+// b is in the level's storage, or level-major when b_level is set.  With
+// xout, x is also written there in level-major order (the end of a solve:
+// the copy of the iterate to the caller rides on this pass).
 template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, const double *__restrict__ x,
-                                                             const double *__restrict__ b,
+                                                             const double *__restrict__ b, int b_level,
                                                              double *__restrict__ r,
                                                              double *__restrict__ xout,
                                                              double *__restrict__ partials)
@@ -911,7 +913,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
                               h * bload(double(), R.rN, R.oc, sk) * (xc - bload(double(), rx, R.on, sk)) +
                               h * bload(double(), R.rN, R.os, sk) * (xc - bload(double(), rx, R.os, sk)) +
                               wU * (xc - xp) + wD * (xc - xm);
-            const double rv = bload(double(), rb, R.oc, sk) - hx;
+            const double bv = b_level ? bload(double(), rb, ol, (unsigned)k * lstride) : bload(double(), rb, R.oc, sk);
+            const double rv = bv - hx;
             if (r) bstore(rv, rr, oo, sk);
             if (xout) bstore(xc, rxo, ol, (unsigned)k * lstride);
             if (active) acc += rv * rv;
@@ -932,12 +935,15 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg_update(size_t n, double *__r
                                                     const double *__restrict__ zold,
                                                     const float *__restrict__ zold32,
                                                     const Scalars *__restrict__ sc,
-                                                    double *__restrict__ partials)
+                                                    double *__restrict__ partials, int x_first)
 {
     const double alpha = sc->alpha;
     double rr = 0, rz = 0;
     for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads) {
-        x[g] += alpha * p[g];
+        if (x_first)
+            x[g] = alpha * p[g];  // first step from x = 0: x is not read
+        else
+            x[g] += alpha * p[g];
         const double rv = r[g] - alpha * q[g];
         r[g] = rv;
         rr += rv * rv;
@@ -1363,15 +1369,15 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     });
 }
 
-hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, double *r, double *xout,
-                           double *partials, int *nblocks_out, hipStream_t s)
+hipError_t launch_residual(const Level<double> &L, const double *x, const double *b, int b_level, double *r,
+                           double *xout, double *partials, int *nblocks_out, hipStream_t s)
 {
     const int kc = stream_kc(L.nz >= 64 && L.plane >= 256 * 256 ? 64 : 16);
     const int G = stream_grid(L, kc);
     *nblocks_out = G;
     return with_kc(kc, [&](auto KCc) {
-        hipLaunchKernelGGL((k_residual<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b, r,
-                           xout, partials);
+        hipLaunchKernelGGL((k_residual<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b, b_level,
+                           r, xout, partials);
         return hipGetLastError();
     });
 }
@@ -1388,11 +1394,12 @@ int cg_ept(int dflt)
 
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q, float *r32,
                              const double *zold, const float *zold32, const Scalars *sc, double *partials,
-                             int *nblocks_out, hipStream_t s)
+                             int x_first, int *nblocks_out, hipStream_t s)
 {
     const int G = grid_for(n, cg_ept(1), kCgThreads);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kCgThreads), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials);
+    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kCgThreads), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials,
+                       x_first);
     return hipGetLastError();
 }
 

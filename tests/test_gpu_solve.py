@@ -106,8 +106,13 @@ def test_warm_start_and_edge_cases():
     assert info2["iterations"] <= 1 and rel_err(host(x2), host(x)) < 1e-12
     z, infoz = H.solve(torch.zeros_like(bt), rtol=1e-8)
     assert infoz["converged"] and infoz["iterations"] == 0 and not host(z).any()
-    _, info0 = H.solve(bt, rtol=1e-8, maxit=0)
+    # no CG update runs: x is exactly the zero initial guess (the solve does
+    # not zero x up front when it starts from x = 0)
+    x0, info0 = H.solve(bt, rtol=1e-8, maxit=0, out=torch.full_like(bt, 7.0))
     assert info0["status"] == 1 and not info0["converged"] and info0["iterations"] == 0
+    assert not host(x0).any() and abs(info0["true_rel_residual"] - 1.0) < 1e-14
+    xr, infor = H.solve(bt, rtol=2.0, out=torch.full_like(bt, 7.0))
+    assert infor["converged"] and infor["iterations"] == 0 and not host(xr).any()
     _, info1 = H.solve(bt, rtol=1e-30, maxit=3)
     assert info1["status"] == 1 and info1["iterations"] == 3
     H.close()
