@@ -782,18 +782,17 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
             {
                 Timed t(h, TPMG_K_PCG_APPLY, s);
                 HIP_TRY(h, launch_pcg_apply(L0, h->z, h->mixed ? h->z32 : nullptr, pold, pnew, h->q, h->sc,
-                                            it == 1, h->partials, &G, s));
+                                            it == 1, flex, h->partials, &G, s));
             }
-            if ((st = finalize(h, G, 1, ST_PQ, flex, s)) != TPMG_OK) return st;
+            // alpha and, flexible, (r_new, z) = (r, z) - alpha (q, z)
+            if ((st = finalize(h, G, flex ? 2 : 1, ST_PQ, flex, s)) != TPMG_OK) return st;
             {
                 Timed t(h, TPMG_K_PCG_UPDATE, s);
-                HIP_TRY(h, launch_pcg_update(n, x, pnew, h->r, h->q, h->mixed ? h->r32 : nullptr,
-                                             (flex && !h->mixed) ? h->z : nullptr,
-                                             (flex && h->mixed) ? h->z32 : nullptr, h->sc, h->partials,
-                                             x_unset ? 1 : 0, &G, s));
+                HIP_TRY(h, launch_pcg_update(n, x, pnew, h->r, h->q, h->mixed ? h->r32 : nullptr, h->sc,
+                                             h->partials, x_unset ? 1 : 0, &G, s));
                 x_unset = false;
             }
-            if ((st = finalize(h, G, 2, ST_RR_RZO, flex, s)) != TPMG_OK) return st;
+            if ((st = finalize(h, G, 1, ST_RR, flex, s)) != TPMG_OK) return st;
             if ((st = read_scalars(h, s)) != TPMG_OK) return st;
             if (h->sc_host->breakdown) {
                 result = TPMG_ERR_BREAKDOWN;

@@ -56,7 +56,7 @@ struct Scalars {
     double bb;        // (b, b)
     double rr;        // (r, r)
     double rz;        // (r, z) of the current z
-    double rzo;       // (r_new, z_old) for the flexible beta
+    double rzo;       // (r_new, z_old) = (r, z) - alpha (q, z), flexible beta
     double pq;        // (p, H p)
     double alpha;
     double beta;
@@ -68,7 +68,6 @@ struct Scalars {
 enum FinalizeStage : int {
     ST_BB = 0,
     ST_RR = 1,
-    ST_RR_RZO = 2,
     ST_RZ_FIRST = 3,
     ST_RZ = 4,
     ST_PQ = 5,
@@ -120,14 +119,16 @@ hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int
 
 // CG building blocks (FP64).  Partial sums go to `partials`; nblocks_out
 // receives the number of partials written per value.
+// p_new = z + beta p_old, q = H p_new, partial sums of (p_new, q) and, with
+// qz, of (q, z) (two values per block)
 hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32,
                             const double *p_old, double *p_new, double *q, const Scalars *sc,
-                            int first, double *partials, int *nblocks_out, hipStream_t s);
-// x += alpha p (x = alpha p without reading x when x_first), r -= alpha q, ...
+                            int first, int qz, double *partials, int *nblocks_out, hipStream_t s);
+// x += alpha p (x = alpha p without reading x when x_first), r -= alpha q,
+// r32 = fl32(r) when given, partial sums of (r, r)
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q,
-                             float *r32, const double *zold, const float *zold32,
-                             const Scalars *sc, double *partials, int x_first, int *nblocks_out,
-                             hipStream_t s);
+                             float *r32, const Scalars *sc, double *partials, int x_first,
+                             int *nblocks_out, hipStream_t s);
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32,
                       double *partials, int *nblocks_out, hipStream_t s);
 // r = b - H x (r null: the norm only) and partial sums of (r, r); b in the

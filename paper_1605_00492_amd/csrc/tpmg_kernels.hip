@@ -809,15 +809,17 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // ---- CG kernels (FP64) -----------------------------------------------------
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = H p_new, and
-// partial sums of (p_new, q).  Neighbour values of p_new are formed on the fly
-// from z and p_old, so p_old and p_new must be different buffers.
+// partial sums of (p_new, q) and, with qz, of (q, z) (flexible CG: then
+// (r - alpha q, z) = (r, z) - alpha (q, z) needs no second pass over z).
+// Neighbour values of p_new are formed on the fly from z and p_old, so p_old
+// and p_new must be different buffers.
 template <int KC>
 __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const double *__restrict__ z,
                                                               const float *__restrict__ z32,
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
                                                               double *__restrict__ q,
-                                                              const Scalars *__restrict__ sc, int first,
+                                                              const Scalars *__restrict__ sc, int first, int qz,
                                                               double *__restrict__ partials)
 {
     int col, k0;
@@ -832,26 +834,30 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     const bool f32 = z32 != nullptr;
     const unsigned zs = (unsigned)tile_width(L.plane) * (f32 ? 4u : 8u);
     const double beta = first ? 0.0 : sc->beta;
-    // p_new at (k, lane offset o in bytes of a double)
-    auto PV = [&](int k, unsigned o) -> double {
-        const double zz = f32 ? (double)bload(float(), rz, o >> 1, (unsigned)k * zs)
-                              : bload(double(), rz, o, (unsigned)k * zs);
+    // z and p_new at (k, lane offset o in bytes of a double)
+    auto ZV = [&](int k, unsigned o) -> double {
+        return f32 ? (double)bload(float(), rz, o >> 1, (unsigned)k * zs) : bload(double(), rz, o, (unsigned)k * zs);
+    };
+    auto PZ = [&](int k, unsigned o, double zz) -> double {
         return first ? zz : zz + beta * bload(double(), rp, o, (unsigned)k * R.pstride);
     };
+    auto PV = [&](int k, unsigned o) -> double { return PZ(k, o, ZV(k, o)); };
     const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     double pm = 0, wD = 0;
     if (k0 > 0) {
         pm = PV(k0 - 1, R.oc);
         wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, (unsigned)(k0 - 1) * R.pstride);
     }
-    double pc = PV(k0, R.oc);
-    double acc_pq = 0;
+    double zc = ZV(k0, R.oc);
+    double pc = PZ(k0, R.oc, zc);
+    double acc_pq = 0, acc_qz = 0;
 #pragma unroll
     for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
             const unsigned sk = (unsigned)k * R.pstride;
-            const double pp = (k + 1 < nz) ? PV(k + 1, R.oc) : 0.0;
+            const double zp = (k + 1 < nz) ? ZV(k + 1, R.oc) : 0.0;
+            const double pp = (k + 1 < nz) ? PZ(k + 1, R.oc, zp) : 0.0;
             const double h = L.wh[k];
             const double wU = L.wz[k] * bload(double(), R.rU, R.oc, sk);
             const double qq = L.mu[k] * pc + h * bload(double(), R.rE, R.oc, sk) * (pc - PV(k, R.oe)) +
@@ -861,14 +867,23 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
                               wD * (pc - pm);
             bstore(pc, rpn, oo, sk);
             bstore(qq, rq, oo, sk);
-            if (active) acc_pq += pc * qq;
+            if (active) {
+                acc_pq += pc * qq;
+                if (qz) acc_qz += qq * zc;
+            }
             pm = pc;
             pc = pp;
+            zc = zp;
             wD = wU;
         }
     }
-    double v[1] = {acc_pq};
-    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+    if (qz) {
+        double v[2] = {acc_pq, acc_qz};
+        block_partials<2>(v, partials, gridDim.x, blockIdx.x);
+    } else {
+        double v[1] = {acc_pq};
+        block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+    }
 }
 
 // r = b - H x (r may be null: the norm only), and partial sums of (r, r).
@@ -927,18 +942,16 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
-// x += alpha p; r -= alpha q; partial (r,r) and, when z_old is given, (r, z_old);
-// optionally r32 = fl32(r) for the FP32 V-cycle.
+// x += alpha p; r -= alpha q; partial sums of (r, r); optionally
+// r32 = fl32(r) for the FP32 V-cycle.
 __global__ __launch_bounds__(kCgThreads) void k_pcg_update(size_t n, double *__restrict__ x,
                                                     const double *__restrict__ p, double *__restrict__ r,
                                                     const double *__restrict__ q, float *__restrict__ r32,
-                                                    const double *__restrict__ zold,
-                                                    const float *__restrict__ zold32,
                                                     const Scalars *__restrict__ sc,
                                                     double *__restrict__ partials, int x_first)
 {
     const double alpha = sc->alpha;
-    double rr = 0, rz = 0;
+    double rr = 0;
     for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads) {
         if (x_first)
             x[g] = alpha * p[g];  // first step from x = 0: x is not read
@@ -948,11 +961,9 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg_update(size_t n, double *__r
         r[g] = rv;
         rr += rv * rv;
         if (r32) r32[g] = (float)rv;
-        if (zold) rz += rv * zold[g];
-        if (zold32) rz += rv * (double)zold32[g];
     }
-    double v[2] = {rr, rz};
-    block_partials<2>(v, partials, gridDim.x, blockIdx.x);
+    double v[1] = {rr};
+    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kCgThreads) void k_dot(size_t n, const double *__restrict__ a,
@@ -996,7 +1007,6 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
     switch (stage) {
     case ST_BB: sc->bb = s0; break;
     case ST_RR: sc->rr = s0; break;
-    case ST_RR_RZO: sc->rr = s0; sc->rzo = s1; break;
     case ST_RZ_FIRST:
         sc->rz = s0;
         sc->beta = 0.0;
@@ -1018,6 +1028,8 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
         } else {
             sc->alpha = a;
         }
+        // flexible: (r - alpha q, z) from (r, z) and s1 = (q, z)
+        if (nvals > 1) sc->rzo = sc->rz - sc->alpha * s1;
         break;
     }
     case ST_TT: sc->tt = s0; break;
@@ -1356,7 +1368,7 @@ hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int
 }
 
 hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32, const double *p_old,
-                            double *p_new, double *q, const Scalars *sc, int first, double *partials,
+                            double *p_new, double *q, const Scalars *sc, int first, int qz, double *partials,
                             int *nblocks_out, hipStream_t s)
 {
     const int kc = stream_kc(L.nz >= 64 && L.plane >= 256 * 256 ? 64 : 16);
@@ -1364,7 +1376,7 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     *nblocks_out = G;
     return with_kc(kc, [&](auto KCc) {
         hipLaunchKernelGGL((k_pcg_apply<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, z, z32, p_old,
-                           p_new, q, sc, first, partials);
+                           p_new, q, sc, first, qz, partials);
         return hipGetLastError();
     });
 }
@@ -1393,13 +1405,11 @@ int cg_ept(int dflt)
 }
 
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q, float *r32,
-                             const double *zold, const float *zold32, const Scalars *sc, double *partials,
-                             int x_first, int *nblocks_out, hipStream_t s)
+                             const Scalars *sc, double *partials, int x_first, int *nblocks_out, hipStream_t s)
 {
     const int G = grid_for(n, cg_ept(1), kCgThreads);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kCgThreads), 0, s, n, x, p, r, q, r32, zold, zold32, sc, partials,
-                       x_first);
+    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kCgThreads), 0, s, n, x, p, r, q, r32, sc, partials, x_first);
     return hipGetLastError();
 }
 
