@@ -337,7 +337,7 @@ def main():
 
     import paper_1605_00492_amd as tp
     import synthetic as syn
-    from paper_1605_00492_amd.binding import K_SWEEP, K_VCYCLE
+    from paper_1605_00492_amd.binding import K_PCG_APPLY, K_SWEEP, K_VCYCLE
 
     w = syn.CONFIGS[args.config]
     dev = torch.device("cuda:0")
@@ -368,8 +368,8 @@ def main():
         lam, info_adj = H.solve(x, rtol=w.rtol, maxit=100)   # dJ/dx = x for J = 0.5 ||x||^2
         g = H.face_gradient(lam, x)
         if record is not None:
-            record.append(dict(info=info, info_adj=info_adj,
-                               sweep=H.profile_read(K_SWEEP), vcycle=H.profile_read(K_VCYCLE)))
+            record.append(dict(info=info, info_adj=info_adj, sweep=H.profile_read(K_SWEEP),
+                               vcycle=H.profile_read(K_VCYCLE), cg_apply=H.profile_read(K_PCG_APPLY)))
         H.close()
         return x, g
 
@@ -396,6 +396,13 @@ def main():
     achieved = sweep_bytes / sweep_avg_s / 1e9
     vc_avg_s = vc_ms / max(vc_n, 1) * 1e-3
     vc_gbs = VCYCLE_WORDS * 4 * w.dof / vc_avg_s / 1e9
+    # The CG direction update + operator apply, the single launch with the
+    # largest share of the step: 52 B/DOF (z32, p_old, 3 faces in FP64; p, q
+    # out), 8 B less on the first iteration of each solve (no p_old).
+    cg_ms, cg_n = r["cg_apply"]
+    cg_avg_s = cg_ms / max(cg_n, 1) * 1e-3
+    cg_bytes = (52 * cg_n - 8 * 2) * w.dof / max(cg_n, 1)   # two solves in the step
+    cg_achieved = cg_bytes / cg_avg_s / 1e9
 
     # Mixed vs plain FP64 solve (solve only, hierarchies already set up).
     Hm = tp.Hierarchy(c, precision="mixed", **kw)
@@ -469,6 +476,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "launch_ms": sweep_avg_s * 1e3, "launches": sweep_n,
                      "algorithmic_bytes_per_launch": sweep_bytes},
+        "roofline_cg": {"kernel": "k_pcg_apply (FP64 CG: p = z + beta p, q = H p)", "bound": "hbm",
+                        "achieved": cg_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": cg_achieved / HBM_PEAK_GBS, "launch_ms": cg_avg_s * 1e3, "launches": cg_n,
+                        "algorithmic_bytes_per_launch": cg_bytes},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a 1/16 sample)")
