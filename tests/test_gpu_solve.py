@@ -66,6 +66,21 @@ def test_fp64_matches_oracle_iterate(work):
     H.close()
 
 
+def test_fp64_flexible_matches_oracle(work):
+    """FP64 V-cycle with the flexible beta: the GPU forms (r_new, z_old) as
+    (r, z) - alpha (q, z) and the oracle takes the dot directly; the iterates
+    agree to rounding at the oracle's iteration count."""
+    w = work["w"]
+    x_of, info_of = work["P"].pcg(work["b"], rtol=w.rtol, maxit=100, flexible=True)
+    H = hier(w, work["c"])
+    x, info = H.solve(to_dev(work["b"]), rtol=w.rtol, maxit=info_of["iterations"], flexible=True)
+    err = rel_err(host(x), x_of)
+    print(f"[gpu] {w.name} fp64 flexible: {info['iterations']} it (oracle {info_of['iterations']}), "
+          f"error vs oracle {err:.2e}", flush=True)
+    assert info["iterations"] == info_of["iterations"] and err <= 1e-10
+    H.close()
+
+
 @pytest.mark.parametrize("flexible", [True, False])
 def test_mixed_reaches_fp64_accuracy(work, flexible):
     w = work["w"]
