@@ -813,10 +813,15 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // partial sums of (p_new, q) and, with qz, of (q, z) (flexible CG: then
 // (r - alpha q, z) = (r, z) - alpha (q, z) needs no second pass over z).
 // Neighbour values of p_new are formed on the fly from z and p_old, so p_old
-// and p_new must be different buffers.
-template <int KC>
-__global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const double *__restrict__ z,
-                                                              const float *__restrict__ z32,
+// and p_new must be different buffers.  z is FP32 (mixed) or FP64 (ZT).
+//
+// The kernel is bound by memory latency (its wavefronts walk their k-chunk
+// level by level), so each wavefront issues level k + 1's loads before it
+// forms level k, and holds z in its stored type until it is used: two
+// levels in flight at 80 VGPRs (6 wavefronts per SIMD) instead of one at
+// 54 (8 per SIMD); 1.45 vs 1.74 ms at 1024^2 x 128 with FP32 z.
+template <int KC, typename ZT>
+__global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const ZT *__restrict__ zt,
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
                                                               double *__restrict__ q,
@@ -829,43 +834,70 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     const int nz = L.nz;
     const StencilRows<double> R(L, col);
     const size_t n = (size_t)nz * L.plane;
-    const Rsrc rz = z32 ? make_rsrc(z32, n * 4) : make_rsrc(z, n * 8);
+    constexpr unsigned ZS = sizeof(ZT);
+    const Rsrc rz = make_rsrc(zt, n * ZS);
     const Rsrc rp = make_rsrc(p_old, first ? 0 : n * 8);
     const Rsrc rpn = make_rsrc(p_new, n * 8), rq = make_rsrc(q, n * 8);
-    const bool f32 = z32 != nullptr;
-    const unsigned zs = (unsigned)tile_width(L.plane) * (f32 ? 4u : 8u);
+    const unsigned zs = (unsigned)tile_width(L.plane) * ZS;
     const double beta = first ? 0.0 : sc->beta;
-    // z and p_new at (k, lane offset o in bytes of a double)
-    auto ZV = [&](int k, unsigned o) -> double {
-        return f32 ? (double)bload(float(), rz, o >> 1, (unsigned)k * zs) : bload(double(), rz, o, (unsigned)k * zs);
+    // lane offsets are in bytes of a double; z offsets scale by ZS / 8
+    auto zo = [](unsigned o) { return ZS == 8 ? o : o >> 1; };
+    auto ZL = [&](int k, unsigned o) -> ZT { return bload(ZT(), rz, zo(o), (unsigned)k * zs); };
+    auto PL = [&](int k, unsigned o) -> double {
+        return first ? 0.0 : bload(double(), rp, o, (unsigned)k * R.pstride);
     };
-    auto PZ = [&](int k, unsigned o, double zz) -> double {
-        return first ? zz : zz + beta * bload(double(), rp, o, (unsigned)k * R.pstride);
+    auto comb = [&](ZT zz, double pp) -> double { return first ? (double)zz : (double)zz + beta * pp; };
+    struct Raw {
+        ZT zE, zW, zN, zS, zu;
+        double pE, pW, pN, pS, pu, cE, cEw, cN, cNs, cU;
     };
-    auto PV = [&](int k, unsigned o) -> double { return PZ(k, o, ZV(k, o)); };
+    auto load = [&](int k) {
+        Raw w;
+        const unsigned sk = (unsigned)k * R.pstride;
+        w.zE = ZL(k, R.oe);
+        w.zW = ZL(k, R.ow);
+        w.zN = ZL(k, R.on);
+        w.zS = ZL(k, R.os);
+        w.pE = PL(k, R.oe);
+        w.pW = PL(k, R.ow);
+        w.pN = PL(k, R.on);
+        w.pS = PL(k, R.os);
+        w.cE = bload(double(), R.rE, R.oc, sk);
+        w.cEw = bload(double(), R.rE, R.ow, sk);
+        w.cN = bload(double(), R.rN, R.oc, sk);
+        w.cNs = bload(double(), R.rN, R.os, sk);
+        w.cU = bload(double(), R.rU, R.oc, sk);
+        w.zu = ZT(0);
+        w.pu = 0.0;
+        if (k + 1 < nz) {
+            w.zu = ZL(k + 1, R.oc);
+            w.pu = PL(k + 1, R.oc);
+        }
+        return w;
+    };
     const unsigned oo = active ? R.oc : 0xFFFFFFFFu;
     double pm = 0, wD = 0;
     if (k0 > 0) {
-        pm = PV(k0 - 1, R.oc);
+        pm = comb(ZL(k0 - 1, R.oc), PL(k0 - 1, R.oc));
         wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, (unsigned)(k0 - 1) * R.pstride);
     }
-    double zc = ZV(k0, R.oc);
-    double pc = PZ(k0, R.oc, zc);
+    double zc = (double)ZL(k0, R.oc);
+    double pc = first ? zc : zc + beta * PL(k0, R.oc);
     double acc_pq = 0, acc_qz = 0;
+    Raw cur = load(k0);
 #pragma unroll
     for (int t = 0; t < KC; ++t) {
         const int k = k0 + t;
         if (k < nz) {
+            Raw nxt = cur;
+            if (t + 1 < KC && k + 1 < nz) nxt = load(k + 1);
             const unsigned sk = (unsigned)k * R.pstride;
-            const double zp = (k + 1 < nz) ? ZV(k + 1, R.oc) : 0.0;
-            const double pp = (k + 1 < nz) ? PZ(k + 1, R.oc, zp) : 0.0;
+            const double zp = (double)cur.zu, pp = comb(cur.zu, cur.pu);
             const double h = L.wh[k];
-            const double wU = L.wz[k] * bload(double(), R.rU, R.oc, sk);
-            const double qq = L.mu[k] * pc + h * bload(double(), R.rE, R.oc, sk) * (pc - PV(k, R.oe)) +
-                              h * bload(double(), R.rE, R.ow, sk) * (pc - PV(k, R.ow)) +
-                              h * bload(double(), R.rN, R.oc, sk) * (pc - PV(k, R.on)) +
-                              h * bload(double(), R.rN, R.os, sk) * (pc - PV(k, R.os)) + wU * (pc - pp) +
-                              wD * (pc - pm);
+            const double wU = L.wz[k] * cur.cU;
+            const double qq = L.mu[k] * pc + h * cur.cE * (pc - comb(cur.zE, cur.pE)) +
+                              h * cur.cEw * (pc - comb(cur.zW, cur.pW)) + h * cur.cN * (pc - comb(cur.zN, cur.pN)) +
+                              h * cur.cNs * (pc - comb(cur.zS, cur.pS)) + wU * (pc - pp) + wD * (pc - pm);
             bstore(pc, rpn, oo, sk);
             bstore(qq, rq, oo, sk);
             if (active) {
@@ -876,6 +908,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             pc = pp;
             zc = zp;
             wD = wU;
+            cur = nxt;
         }
     }
     if (qz) {
@@ -1372,12 +1405,19 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
                             double *p_new, double *q, const Scalars *sc, int first, int qz, double *partials,
                             int *nblocks_out, hipStream_t s)
 {
-    const int kc = stream_kc(L.nz >= 64 && L.plane >= 256 * 256 ? 64 : 16);
+    // 16-level chunks (1024^2 x 128, FP32 z: 1.45 ms vs 1.47 at 32; at 64 the
+    // two levels in flight need 92 VGPRs)
+    const int kc = stream_kc(16);
     const int G = stream_grid(L, kc);
     *nblocks_out = G;
     return with_kc(kc, [&](auto KCc) {
-        hipLaunchKernelGGL((k_pcg_apply<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, z, z32, p_old,
-                           p_new, q, sc, first, qz, partials);
+        constexpr int K = decltype(KCc)::value;
+        if (z32)
+            hipLaunchKernelGGL((k_pcg_apply<K, float>), dim3(G), dim3(kStreamThreads), 0, s, L, z32, p_old, p_new, q,
+                               sc, first, qz, partials);
+        else
+            hipLaunchKernelGGL((k_pcg_apply<K, double>), dim3(G), dim3(kStreamThreads), 0, s, L, z, p_old, p_new, q,
+                               sc, first, qz, partials);
         return hipGetLastError();
     });
 }
