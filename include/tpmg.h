@@ -102,8 +102,16 @@ typedef struct {
     double rtol;         /* stop when ||r||_2 <= rtol ||b||_2 (recursive residual)            */
     int32_t maxit;       /* iteration limit (>= 0)                                            */
     int32_t x0_nonzero;  /* 1: x holds the initial guess; 0: start from x = 0                 */
-    int32_t flexible;    /* 1: beta = (r, z - z_old)/(r_old, z_old) (for the FP32 V-cycle)    */
+    int32_t flexible;    /* 1: flexible CG, beta = -(z, H p)/(p, H p) with p the last
+                            direction (FCG(1): the new direction is H-conjugate to it);
+                            for the FP32 V-cycle, a preconditioner that is not exactly
+                            stationary (Sec. 5 asks for a flexible Krylov method then).
+                            0: beta = (r, z)/(r_old, z_old)                                 */
     double *history;     /* host [maxit+1] for ||r_i||/||b||, or NULL                         */
+    double omega_alt;    /* 0, or in (0, 1]: V-cycles with an odd index (the first is 0) use
+                            this damping instead of the hierarchy's omega, which makes the
+                            preconditioner change between iterations (exercises the flexible
+                            recurrence); the hierarchy's omega is restored on return          */
 } tpmg_solve_opts;
 
 typedef struct {

@@ -22,14 +22,30 @@ _SRC = [os.path.join(_HERE, "tpmg_oracle.c"), os.path.join(_HERE, "oracle_level.
         os.path.join(_HERE, "oracle_mixed.inc")]
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C, no GPU code)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC[0], "-lm"])
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+# Portable optimised build: the library is built on one host and may be loaded
+# on another, so it targets x86-64-v3 (AVX2, FMA) rather than the build host.
+# Floating-point contraction stays off, so every operation rounds as written.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-std=c11", "-fPIC", "-shared"]
+# Build tuned for the host that runs it (for timing the oracle on that host).
+NATIVE_CFLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-std=c11", "-fPIC", "-shared"]
+
+
+def build(force: bool = True, path: str = LIB_PATH, native: bool = False) -> str:
+    """Compile the oracle library with gcc (plain C, no GPU code)."""
+    if not force and os.path.exists(path):
+        return path
+    tmp = path + ".tmp"
+    flags = NATIVE_CFLAGS if native else CFLAGS
+    subprocess.check_call(["gcc", *flags, "-o", tmp, _SRC[0], "-lm"])
+    os.replace(tmp, path)
+    return path
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same sources (e.g. native)."""
+    global _lib, LIB_PATH
+    LIB_PATH = path
+    _lib = None
 
 
 _lib = None
@@ -59,7 +75,7 @@ def lib():
             getattr(L, f"oracle_coarse_solve{name}").argtypes = [vp, p, p]
         L.oracle_dense.argtypes = [vp, C.c_int, _dp]
         L.oracle_pcg.argtypes = [vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
-                                 vp, _dp]
+                                 C.c_double, vp, _dp, vp, vp]
         L.oracle_pcg.restype = C.c_int
         L.oracle_face_gradient.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_mixed_apply.argtypes = [vp, _dp, _dp]
@@ -186,21 +202,32 @@ class Problem:
         out[np.ix_(perm, perm)] = A
         return out
 
-    def pcg(self, b, rtol=1e-8, maxit=100, x0=None, mixed=False, flexible=False):
+    def pcg(self, b, rtol=1e-8, maxit=100, x0=None, mixed=False, flexible=False, omega_alt=0.0,
+            trace=False):
         """Returns (x, info) with info = dict(status, iterations, rel_residual,
-        true_rel_residual, history)."""
+        true_rel_residual, history).  omega_alt > 0: V-cycles with an odd
+        index use that damping (a deliberately variable preconditioner).
+        trace: info also holds the direction p of every iteration and the
+        residual after its update (logical layout, shape (iterations, nz, n, n))."""
         bc, n = self._col(b, 0, np.float64)
         x = to_columns(np.asarray(x0, dtype=np.float64)) if x0 is not None else np.zeros_like(bc)
         x = np.ascontiguousarray(x)
         hist = np.zeros(maxit + 1)
         info = np.zeros(3)
+        m = bc.size
+        tp = np.zeros(max(maxit, 1) * m) if trace else None
+        tr = np.zeros(max(maxit, 1) * m) if trace else None
+        vpt = (lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None)
         st = lib().oracle_pcg(self._h, bc, x, float(rtol), int(maxit), 1 if x0 is not None else 0,
-                              1 if mixed else 0, 1 if flexible else 0,
-                              hist.ctypes.data_as(C.c_void_p), info)
+                              1 if mixed else 0, 1 if flexible else 0, float(omega_alt),
+                              hist.ctypes.data_as(C.c_void_p), info, vpt(tp), vpt(tr))
         it = int(info[2])
-        return from_columns(x, n, self.nz), dict(
-            status=st, iterations=it, converged=st >= 0, rel_residual=info[0],
-            true_rel_residual=info[1], history=hist[: it + 1].copy())
+        res = dict(status=st, iterations=it, converged=st >= 0, rel_residual=info[0],
+                   true_rel_residual=info[1], history=hist[: it + 1].copy())
+        if trace:
+            res["directions"] = np.stack([from_columns(tp[i * m:(i + 1) * m], n, self.nz) for i in range(it)])
+            res["residuals"] = np.stack([from_columns(tr[i * m:(i + 1) * m], n, self.nz) for i in range(it)])
+        return from_columns(x, n, self.nz), res
 
     def face_gradient(self, lam, x) -> np.ndarray:
         lc, n = self._col(lam, 0, np.float64)

@@ -25,7 +25,9 @@
  *   - the velocity-pressure system around it, its Schur-complement
  *     preconditioner and the outer flexible GMRES (oracle_mixed.inc).
  *
- * Dot products accumulate in long double.
+ * Dot products accumulate in long double.  Loops over columns and vector
+ * entries run as OpenMP `parallel for` when built with -fopenmp; nothing
+ * depends on the thread count (dot products sum fixed blocks in order).
  */
 #include <math.h>
 #include <stdint.h>
@@ -145,6 +147,7 @@ oracle_problem *oracle_create(int n, int nz, int nlevels, double a_h, double a_z
             memcpy(L->cU, cU, sizeof(double) * m);
         } else {
             const level_d *Fi = &H->lev[l - 1];
+#pragma omp parallel for schedule(static)
             for (int J = 0; J < L->n; ++J)
                 for (int I = 0; I < L->n; ++I)
                     for (int k = 0; k < nz; ++k) {
@@ -179,6 +182,7 @@ oracle_problem *oracle_create(int n, int nz, int nlevels, double a_h, double a_z
         M->mu = (float *)malloc(sizeof(float) * nz);
         M->wh = (float *)malloc(sizeof(float) * nz);
         M->wz = (float *)malloc(sizeof(float) * nz);
+#pragma omp parallel for schedule(static)
         for (long p = 0; p < m; ++p) {
             M->cE[p] = (float)L->cE[p];
             M->cN[p] = (float)L->cN[p];
@@ -253,23 +257,54 @@ void oracle_vcycle(const oracle_problem *P, const double *b, double *z) { vcycle
 void oracle_vcycle_f(const oracle_problem *P, const float *b, float *z) { vcycle_f(&P->hf, 0, b, z); }
 void oracle_dense(const oracle_problem *P, int l, double *A) { dense_d(&P->hd.lev[l], A); }
 
+/*
+ * (a, b) accumulated in long double: the entries are summed in fixed blocks
+ * of DOT_BLOCK consecutive products, then the block sums in order, so the
+ * result does not depend on the number of threads.
+ */
+#define DOT_BLOCK 4096
 static double dot(const double *a, const double *b, long m)
 {
+    long nb = (m + DOT_BLOCK - 1) / DOT_BLOCK;
+    long double *part = (long double *)malloc(sizeof(long double) * (size_t)(nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nb; ++q) {
+        long double s = 0;
+        long hi = (q + 1) * DOT_BLOCK < m ? (q + 1) * DOT_BLOCK : m;
+        for (long p = q * DOT_BLOCK; p < hi; ++p) s += (long double)a[p] * (long double)b[p];
+        part[q] = s;
+    }
     long double s = 0;
-    for (long p = 0; p < m; ++p) s += (long double)a[p] * (long double)b[p];
+    for (long q = 0; q < nb; ++q) s += part[q];
+    free(part);
     return (double)s;
 }
 
-/* z = V(r): the double V-cycle, or the float V-cycle on fl32(r) returned as double. */
-static void precondition(const oracle_problem *P, int mixed, const double *r, double *z, float *r32, float *z32, long m)
+/*
+ * z = V(r): the double V-cycle, or the float V-cycle on fl32(r) returned as
+ * double, with damping omega in every sweep.
+ */
+static void precondition_omega(const oracle_problem *P, int mixed, double omega, const double *r, double *z,
+                               float *r32, float *z32, long m)
 {
     if (!mixed) {
-        vcycle_d(&P->hd, 0, r, z);
+        hier_d H = P->hd;
+        H.omega = omega;
+        vcycle_d(&H, 0, r, z);
         return;
     }
+    hier_f G = P->hf;
+    G.omega = (float)omega;
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < m; ++p) r32[p] = (float)r[p];
-    vcycle_f(&P->hf, 0, r32, z32);
+    vcycle_f(&G, 0, r32, z32);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < m; ++p) z[p] = (double)z32[p];
+}
+
+static void precondition(const oracle_problem *P, int mixed, const double *r, double *z, float *r32, float *z32, long m)
+{
+    precondition_omega(P, mixed, P->hd.omega, r, z, r32, z32, m);
 }
 
 /*
@@ -277,30 +312,49 @@ static void precondition(const oracle_problem *P, int mixed, const double *r, do
  *   r = b - H x0, z = V r, p = z
  *   repeat: q = H p; alpha = (r,z)/(p,q); x += alpha p; r -= alpha q;
  *           stop when ||r|| <= rtol ||b||;
- *           z_new = V r; beta = (r,z_new)/(r_old,z_old)
- *           [flexible: beta = (r, z_new - z_old)/(r_old,z_old)]; p = z_new + beta p
+ *           z_new = V r;
+ *           standard: beta = (r,z_new)/(r_old,z_old);
+ *           flexible: beta = -(z_new, q)/(p, q), the choice that makes the new
+ *             direction H-conjugate to the last one whatever the
+ *             preconditioner did (flexible CG with one stored direction,
+ *             FCG(1) of Notay 2000; equal to (z_new, r - r_old)/(r_old, z_old));
+ *           p = z_new + beta p
+ * Sec. 5 notes that a preconditioner that changes between iterations needs
+ * a flexible Krylov method; the FP32 V-cycle is such a preconditioner.
+ *
+ * omega_alt > 0 makes the preconditioner deliberately variable: the
+ * applications of V with an odd index (the first is index 0) use the damping
+ * omega_alt instead of the hierarchy's omega.  This exercises the flexible
+ * recurrence with an SPD preconditioner that changes between iterations.
+ *
  * Returns the number of iterations (applications of H to p), or -1 when the
  * iteration limit was reached, -2 on breakdown.  history[0..it] holds
- * ||r_i|| / ||b|| when non-NULL; info = {rel_residual, true_rel_residual}.
+ * ||r_i|| / ||b|| when non-NULL; info = {rel_residual, true_rel_residual,
+ * iterations}.  When trace_p / trace_r are non-NULL (each maxit * m values)
+ * they receive, for iteration i = 1, 2, ..., the direction p it used and the
+ * residual r after its update, at offset (i - 1) * m.
  */
 int oracle_pcg(const oracle_problem *P, const double *b, double *x, double rtol, int maxit,
-               int x0_nonzero, int mixed, int flexible, double *history, double *info)
+               int x0_nonzero, int mixed, int flexible, double omega_alt, double *history, double *info,
+               double *trace_p, double *trace_r)
 {
     const level_d *L = &P->hd.lev[0];
     long m = ncell(L->n, L->nz);
     double *r = (double *)malloc(sizeof(double) * m);
     double *z = (double *)malloc(sizeof(double) * m);
-    double *zo = (double *)malloc(sizeof(double) * m);
     double *p = (double *)malloc(sizeof(double) * m);
     double *q = (double *)malloc(sizeof(double) * m);
     float *r32 = mixed ? (float *)malloc(sizeof(float) * m) : NULL;
     float *z32 = mixed ? (float *)malloc(sizeof(float) * m) : NULL;
-    int status = -1, it = 0;
+    int status = -1, it = 0, napply = 0;
+#define OMEGA_NEXT() ((omega_alt > 0 && (napply++ % 2) == 1) ? omega_alt : P->hd.omega)
 
     if (x0_nonzero) {
         apply_d(L, x, q);
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) r[i] = b[i] - q[i];
     } else {
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) { x[i] = 0; r[i] = b[i]; }
     }
     double bnorm = sqrt(dot(b, b, m));
@@ -312,7 +366,7 @@ int oracle_pcg(const oracle_problem *P, const double *b, double *x, double rtol,
         status = 0;
         goto done;
     }
-    precondition(P, mixed, r, z, r32, z32, m);
+    precondition_omega(P, mixed, OMEGA_NEXT(), r, z, r32, z32, m);
     memcpy(p, z, sizeof(double) * m);
     double rz = dot(r, z, m);
     for (it = 1; it <= maxit; ++it) {
@@ -320,29 +374,34 @@ int oracle_pcg(const oracle_problem *P, const double *b, double *x, double rtol,
         double pq = dot(p, q, m);
         if (!(pq > 0) || !isfinite(rz)) { status = -2; break; }
         double alpha = rz / pq;
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        if (trace_p) memcpy(trace_p + (long)(it - 1) * m, p, sizeof(double) * m);
+        if (trace_r) memcpy(trace_r + (long)(it - 1) * m, r, sizeof(double) * m);
         rnorm = sqrt(dot(r, r, m));
         rel = rnorm / bnorm;
         if (history) history[it] = rel;
         if (rnorm <= rtol * bnorm) { status = it; break; }
         if (it == maxit) break;
-        memcpy(zo, z, sizeof(double) * m);
-        precondition(P, mixed, r, z, r32, z32, m);
+        precondition_omega(P, mixed, OMEGA_NEXT(), r, z, r32, z32, m);
         double rz_new = dot(r, z, m);
-        double beta = flexible ? (rz_new - dot(r, zo, m)) / rz : rz_new / rz;
+        double beta = flexible ? -dot(z, q, m) / pq : rz_new / rz;
         rz = rz_new;
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) p[i] = z[i] + beta * p[i];
     }
+#undef OMEGA_NEXT
     if (it > maxit) it = maxit;
 done:
     if (info) {
         apply_d(L, x, q);
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) q[i] = b[i] - q[i];
         info[0] = rel;
         info[1] = bnorm > 0 ? sqrt(dot(q, q, m)) / bnorm : 0;
         info[2] = it;
     }
-    free(r); free(z); free(zo); free(p); free(q); free(r32); free(z32);
+    free(r); free(z); free(p); free(q); free(r32); free(z32);
     return status;
 }
 
@@ -356,6 +415,7 @@ void oracle_face_gradient(const oracle_problem *P, const double *lam, const doub
                           double *gE, double *gN, double *gU)
 {
     const level_d *L = &P->hd.lev[0];
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->n; ++j)
         for (int i = 0; i < L->n; ++i)
             for (int k = 0; k < L->nz; ++k) {

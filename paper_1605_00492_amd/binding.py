@@ -49,7 +49,7 @@ class Desc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("x0_nonzero", C.c_int32),
-                ("flexible", C.c_int32), ("history", C.c_void_p)]
+                ("flexible", C.c_int32), ("history", C.c_void_p), ("omega_alt", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -240,8 +240,10 @@ class Hierarchy:
 
     def solve(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 100,
               x0: torch.Tensor | None = None, flexible: bool | None = None,
-              out: torch.Tensor | None = None, history: bool = False):
-        """Returns (x, info dict).  Raises on breakdown or argument errors."""
+              out: torch.Tensor | None = None, history: bool = False, omega_alt: float = 0.0):
+        """Returns (x, info dict).  Raises on breakdown or argument errors.
+        omega_alt > 0: V-cycles with an odd index use that damping (a
+        deliberately variable preconditioner)."""
         import numpy as np
         self._cells(b, 0, torch.float64, "b")
         if x0 is not None:
@@ -253,6 +255,7 @@ class Hierarchy:
         opts.rtol, opts.maxit = float(rtol), int(maxit)
         opts.x0_nonzero = 1 if x0 is not None else 0
         opts.flexible = int(self.mixed if flexible is None else bool(flexible))
+        opts.omega_alt = float(omega_alt)
         hist = np.zeros(maxit + 1) if history else None
         opts.history = hist.ctypes.data_as(C.c_void_p) if hist is not None else None
         info = SolveInfo()

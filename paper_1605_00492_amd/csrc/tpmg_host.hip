@@ -60,6 +60,9 @@ struct tpmg_hierarchy {
     std::string err;
     bool prof = false;
     EventPool pools[TPMG_K_COUNT];
+    // damping of the sweeps of the next V-cycle: d.omega, except inside a
+    // solve whose options make the preconditioner vary between iterations
+    double omega_run = 0.0;
 };
 
 namespace {
@@ -262,7 +265,7 @@ tpmg_status sweep(const tpmg_hierarchy *h, int l, int mode, const T *u, const T 
     if (l == 0) cls = mode == SWEEP_ZERO ? TPMG_K_SWEEP0 : (mode == SWEEP_GENERAL ? TPMG_K_SWEEP : TPMG_K_PROLSWEEP);
     Timed t(h, cls, s);
     HIP_TRY(const_cast<tpmg_hierarchy *>(h),
-            launch_sweep<T>(level_view<T>(h, l), mode, u, b, out, ec, (T)h->d.omega, s));
+            launch_sweep<T>(level_view<T>(h, l), mode, u, b, out, ec, (T)h->omega_run, s));
     return TPMG_OK;
 }
 
@@ -557,6 +560,7 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
 
     tpmg_hierarchy *h = new tpmg_hierarchy();
     h->d = *desc;
+    h->omega_run = desc->omega;
     if (desc->dz) h->dz.assign(desc->dz, desc->dz + desc->nz);
     h->d.dz = nullptr;
     h->L = desc->nlevels;
@@ -716,7 +720,8 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     if ((st = check_layout(h, layout)) != TPMG_OK || (st = check_ptrs(h, {b_dev, x_dev})) != TPMG_OK) return st;
     if (!opts) return fail(h, TPMG_ERR_INVALID_ARG, "opts is NULL");
     if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->flexible != 0 && opts->flexible != 1) ||
-        (opts->x0_nonzero != 0 && opts->x0_nonzero != 1))
+        (opts->x0_nonzero != 0 && opts->x0_nonzero != 1) ||
+        !(opts->omega_alt == 0.0 || (opts->omega_alt > 0.0 && opts->omega_alt <= 1.0)))
         return fail(h, TPMG_ERR_INVALID_ARG, "bad solve options");
     if ((const void *)b_dev == (const void *)x_dev) return fail(h, TPMG_ERR_INVALID_ARG, "b and x must not alias");
     hipStream_t s = as_stream(stream);
@@ -724,6 +729,16 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
     const int plane = h->l64[0].plane;
     const Level<double> L0 = level_view<double>(h, 0);
     const int flex = opts->flexible;
+    // V-cycle number i (the first is 0) uses omega_alt when i is odd and
+    // omega_alt > 0, else the hierarchy's omega
+    int napply = 0;
+    auto next_omega = [&]() {
+        h->omega_run = (opts->omega_alt > 0.0 && (napply++ % 2) == 1) ? opts->omega_alt : h->d.omega;
+    };
+    struct OmegaReset {
+        tpmg_hierarchy *h;
+        ~OmegaReset() { h->omega_run = h->d.omega; }
+    } omega_reset{h};
 
     // b and x in the level's storage order (stage0, stage1)
     double *b = h->stage0, *x = h->stage1;
@@ -774,6 +789,7 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
         result = TPMG_OK;
     } else {
         if (h->mixed && !r32_ready) HIP_TRY(h, launch_cast(h->r, h->r32, n, s));
+        next_omega();
         if ((st = precondition(h, s)) != TPMG_OK) return st;
         HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s));
         if ((st = finalize(h, G, 1, ST_RZ_FIRST, flex, s)) != TPMG_OK) return st;
@@ -782,10 +798,9 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
             {
                 Timed t(h, TPMG_K_PCG_APPLY, s);
                 HIP_TRY(h, launch_pcg_apply(L0, h->z, h->mixed ? h->z32 : nullptr, pold, pnew, h->q, h->sc,
-                                            it == 1, flex, h->partials, &G, s));
+                                            it == 1, h->partials, &G, s));
             }
-            // alpha and, flexible, (r_new, z) = (r, z) - alpha (q, z)
-            if ((st = finalize(h, G, flex ? 2 : 1, ST_PQ, flex, s)) != TPMG_OK) return st;
+            if ((st = finalize(h, G, 1, ST_PQ, flex, s)) != TPMG_OK) return st;  // (p, q), alpha
             {
                 Timed t(h, TPMG_K_PCG_UPDATE, s);
                 HIP_TRY(h, launch_pcg_update(n, x, pnew, h->r, h->q, h->mixed ? h->r32 : nullptr, h->sc,
@@ -813,9 +828,12 @@ tpmg_status tpmg_solve(const tpmg_hierarchy *hc, const double *b_dev, double *x_
                 break;
             }
             if (it == opts->maxit) break;
+            next_omega();
             if ((st = precondition(h, s)) != TPMG_OK) return st;
-            HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s));
-            if ((st = finalize(h, G, 1, ST_RZ, flex, s)) != TPMG_OK) return st;
+            // (r, z) and, flexible, (q, z) with q = H p of this iteration
+            HIP_TRY(h, launch_dot(n, h->r, h->z, h->mixed ? h->z32 : nullptr, h->partials, &G, s,
+                                  flex ? h->q : nullptr));
+            if ((st = finalize(h, G, flex ? 2 : 1, ST_RZ, flex, s)) != TPMG_OK) return st;
             std::swap(pold, pnew);
         }
         if (it > opts->maxit) it = opts->maxit;

@@ -56,8 +56,7 @@ struct Scalars {
     double bb;        // (b, b)
     double rr;        // (r, r)
     double rz;        // (r, z) of the current z
-    double rzo;       // (r_new, z_old) = (r, z) - alpha (q, z), flexible beta
-    double pq;        // (p, H p)
+    double pq;        // (p, H p) of the last direction
     double alpha;
     double beta;
     double tt;        // (b - H x, b - H x) of the final iterate
@@ -119,18 +118,19 @@ hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int
 
 // CG building blocks (FP64).  Partial sums go to `partials`; nblocks_out
 // receives the number of partials written per value.
-// p_new = z + beta p_old, q = H p_new, partial sums of (p_new, q) and, with
-// qz, of (q, z) (two values per block)
+// p_new = z + beta p_old, q = H p_new, partial sums of (p_new, q)
 hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32,
                             const double *p_old, double *p_new, double *q, const Scalars *sc,
-                            int first, int qz, double *partials, int *nblocks_out, hipStream_t s);
+                            int first, double *partials, int *nblocks_out, hipStream_t s);
 // x += alpha p (x = alpha p without reading x when x_first), r -= alpha q,
 // r32 = fl32(r) when given, partial sums of (r, r)
 hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, const double *q,
                              float *r32, const Scalars *sc, double *partials, int x_first,
                              int *nblocks_out, hipStream_t s);
+// partial sums of (a, b) and, when c is given, of (c, b) (two values per
+// block); b is b32 when given
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32,
-                      double *partials, int *nblocks_out, hipStream_t s);
+                      double *partials, int *nblocks_out, hipStream_t s, const double *c = nullptr);
 // r = b - H x (r null: the norm only) and partial sums of (r, r); b in the
 // level's storage, or level-major with b_level; with xout non-null, x is also
 // copied there in level-major order.

@@ -810,9 +810,7 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // ---- CG kernels (FP64) -----------------------------------------------------
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = H p_new, and
-// partial sums of (p_new, q) and, with qz, of (q, z) (flexible CG: then
-// (r - alpha q, z) = (r, z) - alpha (q, z) needs no second pass over z).
-// Neighbour values of p_new are formed on the fly from z and p_old, so p_old
+// partial sums of (p_new, q).  Neighbour values of p_new are formed on the fly from z and p_old, so p_old
 // and p_new must be different buffers.  z is FP32 (mixed) or FP64 (ZT).
 //
 // The kernel is bound by memory latency (its wavefronts walk their k-chunk
@@ -825,7 +823,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
                                                               double *__restrict__ q,
-                                                              const Scalars *__restrict__ sc, int first, int qz,
+                                                              const Scalars *__restrict__ sc, int first,
                                                               double *__restrict__ partials)
 {
     int col, k0;
@@ -881,9 +879,9 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
         pm = comb(ZL(k0 - 1, R.oc), PL(k0 - 1, R.oc));
         wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, (unsigned)(k0 - 1) * R.pstride);
     }
-    double zc = (double)ZL(k0, R.oc);
+    const double zc = (double)ZL(k0, R.oc);
     double pc = first ? zc : zc + beta * PL(k0, R.oc);
-    double acc_pq = 0, acc_qz = 0;
+    double acc_pq = 0;
     Raw cur = load(k0);
 #pragma unroll
     for (int t = 0; t < KC; ++t) {
@@ -892,7 +890,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             Raw nxt = cur;
             if (t + 1 < KC && k + 1 < nz) nxt = load(k + 1);
             const unsigned sk = (unsigned)k * R.pstride;
-            const double zp = (double)cur.zu, pp = comb(cur.zu, cur.pu);
+            const double pp = comb(cur.zu, cur.pu);
             const double h = L.wh[k];
             const double wU = L.wz[k] * cur.cU;
             const double qq = L.mu[k] * pc + h * cur.cE * (pc - comb(cur.zE, cur.pE)) +
@@ -900,24 +898,15 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
                               h * cur.cNs * (pc - comb(cur.zS, cur.pS)) + wU * (pc - pp) + wD * (pc - pm);
             bstore(pc, rpn, oo, sk);
             bstore(qq, rq, oo, sk);
-            if (active) {
-                acc_pq += pc * qq;
-                if (qz) acc_qz += qq * zc;
-            }
+            if (active) acc_pq += pc * qq;
             pm = pc;
             pc = pp;
-            zc = zp;
             wD = wU;
             cur = nxt;
         }
     }
-    if (qz) {
-        double v[2] = {acc_pq, acc_qz};
-        block_partials<2>(v, partials, gridDim.x, blockIdx.x);
-    } else {
-        double v[1] = {acc_pq};
-        block_partials<1>(v, partials, gridDim.x, blockIdx.x);
-    }
+    double v[1] = {acc_pq};
+    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 // r = b - H x (r may be null: the norm only), and partial sums of (r, r).
@@ -1000,15 +989,25 @@ __global__ __launch_bounds__(kCgThreads) void k_pcg_update(size_t n, double *__r
     block_partials<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
+// Partial sums of (a, b) and, when c is given, of (c, b); b is FP64 or, when
+// b32 is given, FP32.
 __global__ __launch_bounds__(kCgThreads) void k_dot(size_t n, const double *__restrict__ a,
                                                     const double *__restrict__ b, const float *__restrict__ b32,
-                                                    double *__restrict__ partials)
+                                                    const double *__restrict__ c, double *__restrict__ partials)
 {
-    double s = 0;
-    for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads)
-        s += a[g] * (b32 ? (double)b32[g] : b[g]);
-    double v[1] = {s};
-    block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+    double s = 0, t = 0;
+    for (size_t g = (size_t)blockIdx.x * kCgThreads + threadIdx.x; g < n; g += (size_t)gridDim.x * kCgThreads) {
+        const double bv = b32 ? (double)b32[g] : b[g];
+        s += a[g] * bv;
+        if (c) t += c[g] * bv;
+    }
+    if (c) {
+        double v[2] = {s, t};
+        block_partials<2>(v, partials, gridDim.x, blockIdx.x);
+    } else {
+        double v[1] = {s};
+        block_partials<1>(v, partials, gridDim.x, blockIdx.x);
+    }
 }
 
 // Fixed-order sum of the partials and the scalar recurrences of CG.
@@ -1047,8 +1046,10 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
         if (!(fabs(s0) <= kDblMax)) sc->breakdown = 1;
         break;
     case ST_RZ: {
-        const double num = flexible ? s0 - sc->rzo : s0;
-        sc->beta = num / sc->rz;
+        // s0 = (r, z_new); flexible (FCG(1)): s1 = (q, z_new) with q = H p of
+        // the last iteration, beta = -(z_new, H p) / (p, H p), which makes the
+        // new direction H-conjugate to the last one
+        sc->beta = flexible ? -s1 / sc->pq : s0 / sc->rz;
         sc->rz = s0;
         if (!(fabs(sc->beta) <= kDblMax)) sc->breakdown = 1;
         break;
@@ -1062,8 +1063,6 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
         } else {
             sc->alpha = a;
         }
-        // flexible: (r - alpha q, z) from (r, z) and s1 = (q, z)
-        if (nvals > 1) sc->rzo = sc->rz - sc->alpha * s1;
         break;
     }
     case ST_TT: sc->tt = s0; break;
@@ -1402,7 +1401,7 @@ hipError_t launch_faces_to_column(const double *src, double *dst, int plane, int
 }
 
 hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float *z32, const double *p_old,
-                            double *p_new, double *q, const Scalars *sc, int first, int qz, double *partials,
+                            double *p_new, double *q, const Scalars *sc, int first, double *partials,
                             int *nblocks_out, hipStream_t s)
 {
     // 16-level chunks (1024^2 x 128, FP32 z: 1.45 ms vs 1.47 at 32; at 64 the
@@ -1414,10 +1413,10 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
         constexpr int K = decltype(KCc)::value;
         if (z32)
             hipLaunchKernelGGL((k_pcg_apply<K, float>), dim3(G), dim3(kStreamThreads), 0, s, L, z32, p_old, p_new, q,
-                               sc, first, qz, partials);
+                               sc, first, partials);
         else
             hipLaunchKernelGGL((k_pcg_apply<K, double>), dim3(G), dim3(kStreamThreads), 0, s, L, z, p_old, p_new, q,
-                               sc, first, qz, partials);
+                               sc, first, partials);
         return hipGetLastError();
     });
 }
@@ -1455,11 +1454,11 @@ hipError_t launch_pcg_update(size_t n, double *x, const double *p, double *r, co
 }
 
 hipError_t launch_dot(size_t n, const double *a, const double *b, const float *b32, double *partials,
-                      int *nblocks_out, hipStream_t s)
+                      int *nblocks_out, hipStream_t s, const double *c)
 {
     const int G = grid_for(n, cg_ept(4), kCgThreads);
     *nblocks_out = G;
-    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kCgThreads), 0, s, n, a, b, b32, partials);
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kCgThreads), 0, s, n, a, b, b32, c, partials);
     return hipGetLastError();
 }
 

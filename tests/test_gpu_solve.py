@@ -67,9 +67,8 @@ def test_fp64_matches_oracle_iterate(work):
 
 
 def test_fp64_flexible_matches_oracle(work):
-    """FP64 V-cycle with the flexible beta: the GPU forms (r_new, z_old) as
-    (r, z) - alpha (q, z) and the oracle takes the dot directly; the iterates
-    agree to rounding at the oracle's iteration count."""
+    """FP64 V-cycle with the flexible beta -(z, H p)/(p, H p): the iterates
+    agree with the oracle's to rounding at its iteration count."""
     w = work["w"]
     x_of, info_of = work["P"].pcg(work["b"], rtol=w.rtol, maxit=100, flexible=True)
     H = hier(w, work["c"])
@@ -78,6 +77,34 @@ def test_fp64_flexible_matches_oracle(work):
     print(f"[gpu] {w.name} fp64 flexible: {info['iterations']} it (oracle {info_of['iterations']}), "
           f"error vs oracle {err:.2e}", flush=True)
     assert info["iterations"] == info_of["iterations"] and err <= 1e-10
+    H.close()
+
+
+def test_variable_preconditioner_flexible_matches_oracle(work):
+    """A preconditioner that changes between iterations (every other V-cycle
+    damped with omega 0.4): there the flexible beta differs from the standard
+    one by O(1), so this pins the GPU's flexible recurrence (a flipped or
+    dropped term diverges from the oracle at once).  FP64 V-cycle, equal
+    iteration count, iterate within 1e-10; the standard beta needs more
+    iterations on the same preconditioner."""
+    w = work["w"]
+    if w.levels == 1:
+        pytest.skip("single-level workload: the variable damping is checked on the multigrid ones")
+    x_of, info_of = work["P"].pcg(work["b"], rtol=w.rtol, maxit=200, flexible=True, omega_alt=0.4)
+    _, info_os = work["P"].pcg(work["b"], rtol=w.rtol, maxit=200, flexible=False, omega_alt=0.4)
+    H = hier(w, work["c"])
+    x, info = H.solve(to_dev(work["b"]), rtol=w.rtol, maxit=info_of["iterations"], flexible=True,
+                      omega_alt=0.4, history=True)
+    err = rel_err(host(x), x_of)
+    print(f"[gpu] {w.name} variable preconditioner, flexible: {info['iterations']} it "
+          f"(oracle {info_of['iterations']}, standard beta {info_os['iterations']}), error vs oracle {err:.2e}",
+          flush=True)
+    assert info["converged"] and info["iterations"] == info_of["iterations"] and err <= 1e-10, (info, err)
+    np.testing.assert_allclose(info["history"], info_of["history"], rtol=1e-6)
+    assert info_os["iterations"] >= info_of["iterations"]
+    # the hierarchy's own damping is back for the next solve
+    x2, info2 = H.solve(to_dev(work["b"]), rtol=w.rtol, maxit=work["info_or"]["iterations"])
+    assert rel_err(host(x2), work["x_or"]) <= 1e-10
     H.close()
 
 

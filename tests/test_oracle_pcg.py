@@ -117,3 +117,59 @@ def test_resolution_independence_fixed_courant():
         w = syn.Workload(f"res{n}", n, 16, levels, 16.0, 1e4, True, "uniform")
         its.append(_iterations(w.coefficients(), w.rhs(), w.dz(), 16.0, levels=levels))
     assert its[2] <= its[1] <= its[0], its
+
+
+def _variable_preconditioner_case():
+    rng = np.random.default_rng(7)
+    n, nz = 16, 8
+    dz = 1.05 ** np.arange(nz)
+    c = refs.random_coeffs(rng, n, nz)
+    A = refs.incidence_operator(c, 1.0, 1e3, dz)   # assembled independently of the oracle
+    P = oracle.Problem(c, a_h=1.0, a_z=1e3, dz=dz, levels=3)
+    b = rng.standard_normal((nz, n, n))
+    return A, P, b
+
+
+def _conjugacy(A, info):
+    """Largest H-cosine between consecutive directions, and largest cosine
+    between each direction and the residual after its update."""
+    D = info["directions"].reshape(info["iterations"], -1)
+    R = info["residuals"].reshape(info["iterations"], -1)
+    conj = max(abs(D[k + 1] @ A @ D[k]) / np.sqrt((D[k + 1] @ A @ D[k + 1]) * (D[k] @ A @ D[k]))
+               for k in range(len(D) - 1))
+    orth = max(abs(R[k] @ D[k]) / (np.linalg.norm(R[k]) * np.linalg.norm(D[k])) for k in range(len(D)))
+    return conj, orth
+
+
+@pytest.mark.parametrize("omega_alt", [0.3, 0.5])
+def test_flexible_beta_keeps_local_conjugacy(omega_alt):
+    """Flexible CG with one stored direction (the reading of Sec. 5's call
+    for a flexible Krylov method): whatever the preconditioner does between
+    iterations, each new direction is H-conjugate to the previous one and the
+    residual after an update is orthogonal to the direction just used.  With
+    every other V-cycle damped differently (an SPD preconditioner that
+    changes between iterations) the standard beta loses the conjugacy by
+    O(1) and needs more iterations, so this check tells the two apart; a
+    flipped or dropped term in the flexible beta fails it."""
+    A, P, b = _variable_preconditioner_case()
+    _, fx = P.pcg(b, rtol=1e-10, maxit=80, flexible=True, omega_alt=omega_alt, trace=True)
+    _, st = P.pcg(b, rtol=1e-10, maxit=80, flexible=False, omega_alt=omega_alt, trace=True)
+    assert fx["converged"] and st["converged"]
+    conj_f, orth_f = _conjugacy(A, fx)
+    conj_s, orth_s = _conjugacy(A, st)
+    assert conj_f <= 1e-12 and orth_f <= 1e-12, (conj_f, orth_f)
+    assert conj_s >= 1e-2, conj_s            # the variable preconditioner really matters
+    assert orth_s <= 1e-12, orth_s           # (the residual property comes from alpha)
+    assert fx["iterations"] < st["iterations"], (fx["iterations"], st["iterations"])
+
+
+def test_flexible_equals_standard_for_a_fixed_preconditioner():
+    """With a fixed SPD preconditioner both betas agree in exact arithmetic:
+    same iterations, iterates equal to rounding."""
+    A, P, b = _variable_preconditioner_case()
+    xf, fx = P.pcg(b, rtol=1e-10, maxit=80, flexible=True, trace=True)
+    xs, st = P.pcg(b, rtol=1e-10, maxit=80, flexible=False, trace=True)
+    assert fx["iterations"] == st["iterations"]
+    assert np.linalg.norm(xf - xs) / np.linalg.norm(xs) <= 1e-10
+    conj, orth = _conjugacy(A, fx)
+    assert conj <= 1e-12 and orth <= 1e-12
