@@ -11,8 +11,10 @@ every face).  Inputs are resident in HBM before the timed region.
 
 Beside the steps the plain FP64 solve is timed on the same input for the
 FP32-MG vs FP64 comparison, the finest-level FP32 sweep kernel is timed with
-HIP events for the roofline line, and the CPU oracle is timed on a bounded
-sample of the same workload.
+HIP events for the roofline line, and the CPU oracle (built for the host,
+OpenMP over columns) runs one step of the same workload on the host's cores.
+`--cpu-baseline` times the oracle's solves on several workloads, single- and
+multi-threaded.
 
 Prints one JSON line.
 """
@@ -61,25 +63,100 @@ def measured_traffic(launch_dof: int):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, syn):
-    """The CPU oracle (plain C, one thread) on a 1/16 column sample of the
-    workload, the whole step timed twice on the same inputs."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def native_oracle():
+    """The oracle built for this host (gcc -O3 -march=native -ffp-contract=off
+    -fopenmp) in a temporary directory, loaded in place of the portable build."""
+    import tempfile
+
     import oracle
-    s = syn.scaled(w, 256, levels=5, name=f"{w.name}@256x256x{w.nz}")
-    c, b = s.coefficients(), s.rhs()
-    reps = 2
+    d = tempfile.mkdtemp(prefix="tpmg_oracle_")
+    path = oracle.build(path=os.path.join(d, "liboracle_native.so"), native=True)
+    oracle.use_library(path)
+    return oracle
+
+
+def oracle_step(oracle, w, c, b):
+    """One step of the path on the oracle: setup, mixed solve, adjoint.
+    Returns (setup_s, solve_s, adjoint_s, forward iterations, adjoint iterations)."""
     t0 = time.perf_counter()
-    for _ in range(reps):
-        P = oracle.problem_for(s, c)
-        x, info = P.pcg(b, rtol=s.rtol, maxit=100, mixed=True, flexible=True)
-        lam, info2 = P.pcg(x, rtol=s.rtol, maxit=100, mixed=True, flexible=True)
-        P.face_gradient(lam, x)
-        del P
-    dt = (time.perf_counter() - t0) / reps
-    return {"value": s.dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{s.n}x{s.n}x{s.nz} columns (1/16 of the grid), same a_z, grading, coefficient law and "
-                      f"16x16 coarsest level; one step = setup + mixed solve ({info['iterations']} it) + "
-                      f"adjoint ({info2['iterations']} it); {reps} steps in {reps * dt:.1f} s"}
+    P = oracle.problem_for(w, c)
+    t1 = time.perf_counter()
+    x, info = P.pcg(b, rtol=w.rtol, maxit=100, mixed=True, flexible=True)
+    t2 = time.perf_counter()
+    lam, info2 = P.pcg(x, rtol=w.rtol, maxit=100, mixed=True, flexible=True)
+    P.face_gradient(lam, x)
+    t3 = time.perf_counter()
+    del P
+    return t1 - t0, t2 - t1, t3 - t2, info["iterations"], info2["iterations"]
+
+
+def cpu_baseline(w, syn):
+    """The CPU oracle (plain C, OpenMP over columns, built for this host) on
+    the whole workload: one step (setup + mixed solve + adjoint) on all the
+    threads OpenMP is given (OMP_NUM_THREADS, else every core)."""
+    oracle = native_oracle()
+    threads = oracle.threads()
+    c, b = w.coefficients(), w.rhs()
+    t_setup, t_solve, t_adj, it, it2 = oracle_step(oracle, w, c, b)
+    dt = t_setup + t_solve + t_adj
+    return {"value": w.dof / dt, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole {w.n}x{w.n}x{w.nz} workload, one step: setup {t_setup:.1f} s, mixed solve "
+                      f"({it} it) {t_solve:.1f} s, adjoint ({it2} it) {t_adj:.1f} s; gcc -O3 -march=native "
+                      f"-fopenmp, {threads} threads on {os.cpu_count()} logical CPUs ({cpu_model()})",
+            "ms_per_step": dt * 1e3}
+
+
+def cpu_protocol(args):
+    """The oracle's time per solve on the host (median of 3 after 1 warm-up,
+    setup timed apart): the 32^2 x 16, 512^2 x 64 and 256^2 x 32 workloads
+    single-threaded and on all threads, the 1024^2 x 128 workload on all
+    threads; FP64 and mixed solves.  One JSON line."""
+    import synthetic as syn
+    oracle = native_oracle()
+    all_threads = oracle.threads()
+    out = {"cpu": cpu_model(), "logical_cpus": os.cpu_count(), "threads_all": all_threads,
+           "build": "gcc -O3 -march=native -ffp-contract=off -fopenmp", "runs": []}
+    plan = [("fp64_ref_32x32x16", (1, all_threads)), ("fp64_512x512x64", (1, all_threads)),
+            ("adjoint_256x256x32", (1, all_threads)), ("large_1024x1024x128", (all_threads,))]
+    for name, thread_counts in plan:
+        if args.cpu_only and name not in args.cpu_only.split(","):
+            continue
+        w = syn.CONFIGS[name]
+        c, b = w.coefficients(), w.rhs()
+        for nt in thread_counts:
+            oracle.threads(nt)
+            t0 = time.perf_counter()
+            P = oracle.problem_for(w, c)
+            setup_s = time.perf_counter() - t0
+            for mixed in (False, True):
+                ts = []
+                for rep in range(4):
+                    t0 = time.perf_counter()
+                    x, info = P.pcg(b, rtol=w.rtol, maxit=100, mixed=mixed, flexible=mixed)
+                    if rep > 0:
+                        ts.append(time.perf_counter() - t0)
+                s = sorted(ts)[1]
+                word = 4 if mixed else 8
+                row = dict(workload=name, dof=w.dof, threads=nt, precision="mixed" if mixed else "fp64",
+                           setup_s=setup_s, solve_s=s, iterations=info["iterations"],
+                           dof_iterations_per_s=w.dof * info["iterations"] / s,
+                           vcycle_model_bytes_per_dof=VCYCLE_WORDS * word)
+                out["runs"].append(row)
+                log(f"cpu {row}")
+            del P
+        oracle.threads(all_threads)
+    print(json.dumps(out), flush=True)
 
 
 def probe(tp, torch, w, c, b, kw, args):
@@ -326,11 +403,18 @@ def main():
                     help="Courant-number and resolution study (single level vs multigrid variants)")
     ap.add_argument("--probe", action="store_true",
                     help="only run the finest-level FP32 sweep and a 1 GiB copy (for counter runs)")
+    ap.add_argument("--cpu-baseline", action="store_true",
+                    help="the oracle's time per solve on this host, single-threaded and on all threads")
+    ap.add_argument("--cpu-only", default=None, help="with --cpu-baseline: comma-separated workload names")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               f"documented but not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_baseline:
+        cpu_protocol(args)
+        return
 
     import numpy as np
     import torch
@@ -482,7 +566,9 @@ def main():
                         "algorithmic_bytes_per_launch": cg_bytes},
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a 1/16 sample)")
+        log("cpu baseline (the oracle on the whole workload, all threads)")
+        del c, b, x, g, xm, x64, xs
+        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(w, syn)
     print(json.dumps(out), flush=True)
 

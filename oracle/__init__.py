@@ -64,6 +64,8 @@ def lib():
         L.oracle_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, vp,
                                     _dp, _dp, _dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int]
         L.oracle_destroy.argtypes = [vp]
+        L.oracle_threads.argtypes = [C.c_int]
+        L.oracle_threads.restype = C.c_int
         L.oracle_level_n.argtypes = [vp, C.c_int]
         L.oracle_level_n.restype = C.c_int
         L.oracle_get_coeffs.argtypes = [vp, C.c_int, _dp, _dp, _dp]
@@ -84,6 +86,11 @@ def lib():
         L.oracle_mixed_fgmres.restype = C.c_int
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0) and return the count in use."""
+    return int(lib().oracle_threads(int(n)))
 
 
 def to_columns(a: np.ndarray) -> np.ndarray:

@@ -33,6 +33,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAX_LEVELS 16
 
@@ -213,6 +216,19 @@ oracle_problem *oracle_create(int n, int nz, int nlevels, double a_h, double a_z
 }
 
 int oracle_level_n(const oracle_problem *P, int l) { return P->hd.lev[l].n; }
+
+/* Threads for the OpenMP loops (n <= 0 leaves the setting alone); the number
+ * the next parallel loop will use. */
+int oracle_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 void oracle_get_coeffs(const oracle_problem *P, int l, double *cE, double *cN, double *cU)
 {

@@ -127,8 +127,8 @@ def test_mixed_reaches_fp64_accuracy(work, flexible):
 
 def test_column_major_solve(work):
     w = work["w"]
-    if w.dof > 2_000_000:
-        pytest.skip("layout check on the smaller workloads")
+    if w.dof > 4_000_000:
+        pytest.skip("layout check on the workloads up to 256 x 256 x 32")
     H = hier(w, np.ascontiguousarray(np.transpose(work["c"], (2, 3, 1, 0))), layout="column")
     bt = to_dev(np.ascontiguousarray(np.transpose(work["b"], (1, 2, 0))))
     it = work["info_or"]["iterations"]
@@ -200,8 +200,8 @@ def test_solve_without_info(work):
 
     from paper_1605_00492_amd import binding as B
     w = work["w"]
-    if w.dof > 2_000_000:
-        pytest.skip("checked on the smaller workloads")
+    if w.dof > 4_000_000:
+        pytest.skip("checked on the workloads up to 256 x 256 x 32")
     for precision, layout in (("fp64", "level"), ("mixed", "level"), ("fp64", "column")):
         c, b = work["c"], work["b"]
         if layout == "column":
