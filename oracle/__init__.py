@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, "tpmg_oracle.c"), os.path.join(_HERE, "oracle_level.inc"),
-        os.path.join(_HERE, "oracle_mixed.inc")]
+        os.path.join(_HERE, "oracle_mixed.inc"), os.path.join(_HERE, "oracle_dg1.inc")]
 
 
 # Portable optimised build: the library is built on one host and may be loaded
@@ -84,6 +84,20 @@ def lib():
         L.oracle_mixed_precondition.argtypes = [vp, C.c_int, _dp, _dp]
         L.oracle_mixed_fgmres.argtypes = [vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int, vp, _dp]
         L.oracle_mixed_fgmres.restype = C.c_int
+        L.oracle_dg1_create.restype = vp
+        L.oracle_dg1_create.argtypes = [vp]
+        L.oracle_dg1_destroy.argtypes = [vp]
+        for fn in ("apply", "line_solve"):
+            getattr(L, f"oracle_dg1_{fn}").argtypes = [vp, _dp, _dp]
+        L.oracle_dg1_smooth.argtypes = [vp, vp, _dp, _dp]
+        L.oracle_dg1_restrict.argtypes = [vp, _dp, _dp]
+        L.oracle_dg1_prolong_add.argtypes = [vp, _dp, _dp]
+        L.oracle_dg1_vcycle.argtypes = [vp, _dp, _dp]
+        L.oracle_dg1_column_block.argtypes = [vp, C.c_int, C.c_int, _dp]
+        L.oracle_dg1_factors.argtypes = [vp, _dp]
+        L.oracle_dg1_dense.argtypes = [vp, _dp]
+        L.oracle_dg1_pcg.argtypes = [vp, _dp, _dp, C.c_double, C.c_int, vp, _dp]
+        L.oracle_dg1_pcg.restype = C.c_int
         _lib = L
     return _lib
 
@@ -277,6 +291,113 @@ class Problem:
         it = int(info[2])
         return self._mixed_logical(x), dict(status=st, iterations=it, converged=st >= 0, rel_residual=info[0],
                                             true_rel_residual=info[1], history=hist[: it + 1].copy())
+
+
+# -- next-to-lowest order: DG1 pressure (6 unknowns per cell) ------------------
+DG1_NB, DG1_KL, DG1_KU = 6, 5, 5
+DG1_NF = DG1_KL + DG1_KU + 1
+
+
+def dg1_to_columns(a: np.ndarray) -> np.ndarray:
+    """(6, nz, n, n) -> the oracle's order [((j*n+i)*nz + k)*6 + a]."""
+    return np.ascontiguousarray(np.transpose(a, (2, 3, 1, 0))).reshape(-1)
+
+
+def dg1_from_columns(a: np.ndarray, n: int, nz: int) -> np.ndarray:
+    return np.ascontiguousarray(a.reshape(n, n, nz, DG1_NB).transpose(3, 2, 0, 1))
+
+
+class DG1:
+    """The DG1 pressure level on the finest grid of a Problem (whose DG0
+    hierarchy is the coarse part of the NLO V-cycle).  Arrays in the logical
+    layout (6, nz, n, n): unknown a = 3 v + h of cell (i, j, k), v = bottom /
+    top value in the vertical, h = 1, xi, eta in the horizontal."""
+
+    def __init__(self, P: Problem):
+        self.P, self.n, self.nz = P, P.n, P.nz
+        self._h = lib().oracle_dg1_create(P._h)
+        if not self._h:
+            raise ValueError("oracle_dg1_create rejected the problem")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.oracle_dg1_destroy(h)
+            self._h = None
+
+    def _in(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        assert x.shape == (DG1_NB, self.nz, self.n, self.n), x.shape
+        return dg1_to_columns(x)
+
+    def _out(self, v):
+        return dg1_from_columns(v, self.n, self.nz)
+
+    def _unary(self, fn, x):
+        xc = self._in(x)
+        y = np.empty_like(xc)
+        getattr(lib(), fn)(self._h, xc, y)
+        return self._out(y)
+
+    def apply(self, x):
+        return self._unary("oracle_dg1_apply", x)
+
+    def line_solve(self, r):
+        return self._unary("oracle_dg1_line_solve", r)
+
+    def vcycle(self, b):
+        return self._unary("oracle_dg1_vcycle", b)
+
+    def smooth(self, u, b):
+        bc = self._in(b)
+        out = np.empty_like(bc)
+        uc = self._in(u) if u is not None else None
+        lib().oracle_dg1_smooth(self._h, uc.ctypes.data_as(C.c_void_p) if uc is not None else None, bc, out)
+        return self._out(out)
+
+    def restrict(self, r):
+        out = np.empty(self.n * self.n * self.nz)
+        lib().oracle_dg1_restrict(self._h, self._in(r), out)
+        return from_columns(out, self.n, self.nz)
+
+    def prolong_add(self, e0, u):
+        uc = self._in(u).copy()
+        lib().oracle_dg1_prolong_add(self._h, to_columns(np.asarray(e0, dtype=np.float64)), uc)
+        return self._out(uc)
+
+    def column_block(self, i, j):
+        m = DG1_NB * self.nz
+        A = np.empty(m * m)
+        lib().oracle_dg1_column_block(self._h, int(i), int(j), A)
+        return A.reshape(m, m)
+
+    def factors(self):
+        """Band LU factors: (n, n, 6 nz, 11) indexed [j, i, row, entry], row
+        r = 6 k + a, entries L(r, r-5..r-1), U(r, r), U(r, r+1..r+5)."""
+        F = np.empty(self.n * self.n * DG1_NB * self.nz * DG1_NF)
+        lib().oracle_dg1_factors(self._h, F)
+        return F.reshape(self.n, self.n, DG1_NB * self.nz, DG1_NF)
+
+    def dense(self):
+        """Dense H1 in the logical order (a, k, j, i)."""
+        M = DG1_NB * self.n * self.n * self.nz
+        A = np.empty(M * M)
+        lib().oracle_dg1_dense(self._h, A)
+        A = A.reshape(M, M)
+        perm = dg1_to_columns(np.arange(M).reshape(DG1_NB, self.nz, self.n, self.n))
+        out = np.empty_like(A)
+        out[np.ix_(perm, perm)] = A
+        return out
+
+    def pcg(self, b, rtol=1e-8, maxit=100):
+        bc = self._in(b)
+        x = np.zeros_like(bc)
+        hist = np.zeros(maxit + 1)
+        info = np.zeros(3)
+        st = lib().oracle_dg1_pcg(self._h, bc, x, float(rtol), int(maxit), hist.ctypes.data_as(C.c_void_p), info)
+        it = int(info[2])
+        return self._out(x), dict(status=st, iterations=it, converged=st >= 0, rel_residual=info[0],
+                                  true_rel_residual=info[1], history=hist[: it + 1].copy())
 
 
 def problem_for(w, c=None, **overrides) -> Problem:

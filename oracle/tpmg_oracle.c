@@ -23,7 +23,10 @@
  *     V-cycle in double or in float;
  *   - the adjoint face gradient dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q);
  *   - the velocity-pressure system around it, its Schur-complement
- *     preconditioner and the outer flexible GMRES (oracle_mixed.inc).
+ *     preconditioner and the outer flexible GMRES (oracle_mixed.inc);
+ *   - the next-to-lowest-order DG1 pressure level with its banded-LU line
+ *     smoother and the p-coarsening to the lowest-order hierarchy
+ *     (oracle_dg1.inc).
  *
  * Dot products accumulate in long double.  Loops over columns and vector
  * entries run as OpenMP `parallel for` when built with -fopenmp; nothing
@@ -449,3 +452,5 @@ void oracle_face_gradient(const oracle_problem *P, const double *lam, const doub
 }
 
 #include "oracle_mixed.inc"
+
+#include "oracle_dg1.inc"

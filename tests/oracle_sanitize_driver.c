@@ -89,6 +89,35 @@ static int run_case(int n, int nz, int levels, int direct, int graded)
         bad += check(st >= 0 && info[1] <= 1e-7, "fgmres converged");
         free(mb); free(mx); free(my);
     }
+    if (nz >= 2) {
+        /* next-to-lowest order: the DG1 level over this hierarchy */
+        oracle_dg1 *G = oracle_dg1_create(P);
+        if (!G) { fprintf(stderr, "oracle_dg1_create failed\n"); return bad + 1; }
+        long M1 = 6 * m, mc = 6 * nz;
+        double *u1 = (double *)malloc(sizeof(double) * M1), *b1 = (double *)malloc(sizeof(double) * M1);
+        double *y1 = (double *)malloc(sizeof(double) * M1), *e0 = (double *)malloc(sizeof(double) * m);
+        double *blk = (double *)malloc(sizeof(double) * mc * mc);
+        double *F = (double *)malloc(sizeof(double) * (long)n * n * mc * DG1_NF);
+        for (long p = 0; p < M1; ++p) { u1[p] = urand() - 0.5; b1[p] = urand() - 0.5; }
+        oracle_dg1_apply(G, u1, y1);
+        oracle_dg1_line_solve(G, b1, y1);
+        oracle_dg1_smooth(G, NULL, b1, y1);
+        oracle_dg1_smooth(G, u1, b1, y1);
+        oracle_dg1_restrict(G, b1, e0);
+        oracle_dg1_prolong_add(G, e0, u1);
+        oracle_dg1_column_block(G, n - 1, 0, blk);
+        oracle_dg1_factors(G, F);
+        oracle_dg1_vcycle(G, b1, y1);
+        if (M1 <= 1200) {
+            double *A1 = (double *)malloc(sizeof(double) * M1 * M1);
+            oracle_dg1_dense(G, A1);
+            free(A1);
+        }
+        int st = oracle_dg1_pcg(G, b1, u1, 1e-10, 300, hist, info);
+        bad += check(st >= 0 && info[1] <= 2e-10, "dg1 pcg converged");
+        oracle_dg1_destroy(G);
+        free(u1); free(b1); free(y1); free(e0); free(blk); free(F);
+    }
     oracle_destroy(P);
     free(c); free(dz); free(b); free(x); free(y); free(lam); free(bf); free(yf); free(g); free(tp); free(tr);
     return bad;
