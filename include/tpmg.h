@@ -154,6 +154,23 @@ tpmg_status tpmg_apply_operator(const tpmg_hierarchy *h, int32_t level, int32_t 
                                 const void *x_dev, void *y_dev, int32_t layout, void *stream);
 
 /*
+ * For callers that cannot allocate device memory or touch a hierarchy's
+ * internal vectors (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): y = H_level x exactly as
+ * tpmg_apply_operator computes it (same kernels, bit-identical results), with
+ * the layout staging in a library-owned static device array of 64 MiB per GPU
+ * (held from the first call on that GPU until the process ends; looked up
+ * with that GPU current) instead of the hierarchy's staging vectors.  It
+ * calls no allocating routine.  At most 32 MiB per staged vector: levels of
+ * up to 4,194,304 cells (fp32 = 0) or 8,388,608 cells (fp32 = 1), else
+ * TPMG_ERR_WORKSPACE before any launch.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams, other threads, other
+ * handles) race.  Call with the hierarchy's GPU current.  Asynchronous.
+ */
+tpmg_status tpmg_apply_operator_static(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *x_dev,
+                                       void *y_dev, int32_t layout, void *stream);
+
+/*
  * z = V b: one V-cycle from a zero initial guess on the finest level (the
  * preconditioner of Sec. 4.2.1).  fp32 as in tpmg_apply_operator.  b, z:
  * n*n*nz values in `layout`; must not alias.

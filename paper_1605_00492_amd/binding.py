@@ -22,6 +22,7 @@ K_SWEEP, K_SWEEP0, K_PROLSWEEP, K_RESTRICT, K_PCG_APPLY, K_PCG_UPDATE, K_VCYCLE 
 
 EXPORTS = [
     "tpmg_workspace_bytes", "tpmg_setup_hierarchy", "tpmg_level_n", "tpmg_apply_operator",
+    "tpmg_apply_operator_static",
     "tpmg_vcycle", "tpmg_solve", "tpmg_face_gradient", "tpmg_smooth", "tpmg_residual_restrict",
     "tpmg_prolong_smooth", "tpmg_coarse_solve", "tpmg_mixed_workspace_bytes", "tpmg_mixed_apply",
     "tpmg_mixed_precondition", "tpmg_mixed_solve", "tpmg_level_coefficients", "tpmg_profile_enable",
@@ -75,6 +76,7 @@ def lib():
         L.tpmg_level_n.argtypes = [vp, i32]
         L.tpmg_level_n.restype = i32
         L.tpmg_apply_operator.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+        L.tpmg_apply_operator_static.argtypes = [vp, i32, i32, vp, vp, i32, vp]
         L.tpmg_vcycle.argtypes = [vp, i32, vp, vp, i32, vp]
         L.tpmg_solve.argtypes = [vp, vp, vp, i32, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.tpmg_face_gradient.argtypes = [vp, vp, vp, vp, i32, vp]
@@ -229,6 +231,16 @@ class Hierarchy:
         _check(lib().tpmg_apply_operator(self.handle, level, self._fp32(x), _ptr(x), _ptr(y),
                                          self.layout, _stream(self.device)),
                "tpmg_apply_operator", self.handle)
+        return y
+
+    def apply_static(self, x: torch.Tensor, level: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = H_level x staged through the library's static device array
+        (no allocation inside the call; see tpmg_apply_operator_static)."""
+        self._cells(x, level)
+        y = torch.empty_like(x) if out is None else out
+        _check(lib().tpmg_apply_operator_static(self.handle, level, self._fp32(x), _ptr(x), _ptr(y),
+                                                self.layout, _stream(self.device)),
+               "tpmg_apply_operator_static", self.handle)
         return y
 
     def vcycle(self, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -527,6 +528,40 @@ tpmg_status coarse_solve_impl(const tpmg_hierarchy *h, const void *b, void *u, h
     return stage_out(h, os, u, l, sizeof(T), s);
 }
 
+// ---- staging memory of tpmg_apply_operator_static -------------------------------
+// A file-scope device array, so that the entry point needs neither an
+// allocation nor the hierarchy's own staging vectors.  Every GPU the library
+// runs on holds its own copy until the process ends.  In host code the name
+// `scratch` is only a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed to
+// kernels.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+tpmg_status static_scratch(tpmg_hierarchy *h, void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, TPMG_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(h, TPMG_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TPMG_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -681,6 +716,37 @@ tpmg_status tpmg_apply_operator(const tpmg_hierarchy *h, int32_t level, int32_t 
     const int elem = fp32 ? 4 : 8;
     const int plane = h->l64[level].plane;
     void *x = h->stage0, *y = h->stage1;
+    HIP_TRY(hm, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, elem, s));
+    if (fp32)
+        HIP_TRY(hm, launch_apply<float>(level_view<float>(h, level), (const float *)x, (float *)y, s));
+    else
+        HIP_TRY(hm, launch_apply<double>(level_view<double>(h, level), (const double *)x, (double *)y, s));
+    HIP_TRY(hm, launch_cells_out(y, y_dev, layout, plane, h->nz, elem, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_apply_operator_static(const tpmg_hierarchy *h, int32_t level, int32_t fp32, const void *x_dev,
+                                       void *y_dev, int32_t layout, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (level < 0 || level >= h->L) return fail(hm, TPMG_ERR_INVALID_ARG, "level out of range");
+    if ((st = check_fp32(h, fp32)) != TPMG_OK || (st = check_layout(h, layout)) != TPMG_OK ||
+        (st = check_ptrs(h, {x_dev, y_dev})) != TPMG_OK)
+        return st;
+    const int elem = fp32 ? 4 : 8;
+    const int plane = h->l64[level].plane;
+    const size_t half = kStaticScratchBytes / 2;
+    if ((size_t)plane * h->nz * elem > half)
+        return fail(hm, TPMG_ERR_WORKSPACE,
+                    "level has " + std::to_string((size_t)plane * h->nz) + " cells; the static scratch stages at most " +
+                        std::to_string(half / elem) + " per vector");
+    void *base = nullptr;
+    if ((st = static_scratch(hm, &base)) != TPMG_OK) return st;
+    // both halves are written in full before they are read: nothing to clear
+    void *x = base, *y = (char *)base + half;
+    hipStream_t s = as_stream(stream);
     HIP_TRY(hm, launch_cells_in(x_dev, layout, x, nullptr, plane, h->nz, elem, s));
     if (fp32)
         HIP_TRY(hm, launch_apply<float>(level_view<float>(h, level), (const float *)x, (float *)y, s));
