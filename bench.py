@@ -336,6 +336,87 @@ def mixed_system(tp, torch, w, dev, args):
     print(json.dumps(out), flush=True)
 
 
+def nlo(tp, torch, dev, args):
+    """The next-to-lowest-order (DG1) workload: band LU of every column block
+    (setup), CG with the NLO V-cycle (DG1 line sweeps, p-coarsening to the
+    lowest-order hierarchy in FP64 or FP32) to rtol 1e-8, and the DG1 general
+    sweep (residual + forward / back substitution + update, one launch) timed
+    with HIP events against its algorithmic bytes: band factors 11 words,
+    u, b, out 3 words and the faces 0.5 word per unknown (116 B).  The oracle
+    (native build, all threads) solves the same system once for the CPU line
+    and the error of the GPU solutions against it.  One JSON line."""
+    import numpy as np
+
+    import synthetic as syn
+    from paper_1605_00492_amd.binding import K_DG1_PCG_APPLY, K_DG1_SWEEP, K_DG1_VCYCLE, K_VCYCLE
+    w = syn.NLO_WORKLOADS[args.nlo_workload]
+    nv = 6 * w.dof
+    c = torch.from_numpy(w.coefficients()).to(dev)
+    b = torch.from_numpy(w.dg1_rhs()).to(dev)
+    kw = dict(dz=w.dz(), a_h=w.a_h, a_z=w.a_z, levels=w.levels, nu=w.nu, omega=w.omega, coarse=w.coarse,
+              n_coarse=w.n_coarse)
+    out = {"workload": w.name, "grid": [w.n, w.n, w.nz], "cells": w.dof, "unknowns": nv,
+           "rows_per_column": 6 * w.nz, "band": [5, 5], "runs": []}
+    sols = {}
+    for prec in ("fp64", "mixed"):
+        H = tp.Hierarchy(c, precision=prec, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D = tp.DG1Level(H)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(args.warmup):
+            D.solve(b, rtol=w.rtol, maxit=200)
+        ts = []
+        for _ in range(max(args.steps, 1)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = D.solve(b, rtol=w.rtol, maxit=200)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = sorted(ts)[len(ts) // 2] * 1e3
+        H.profile_enable(True)
+        D.solve(b, rtol=w.rtol, maxit=200)
+        prof = {name: H.profile_read(cls) for name, cls in (("sweep", K_DG1_SWEEP), ("pcg_apply", K_DG1_PCG_APPLY),
+                                                             ("vcycle", K_DG1_VCYCLE), ("lo_vcycle", K_VCYCLE))}
+        H.profile_enable(False)
+        avg = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+        sweep_bytes = 116 * nv
+        row = dict(precision=prec, setup_ms=setup_ms, solve_ms=ms, iterations=info["iterations"],
+                   true_rel_residual=info["true_rel_residual"],
+                   unknown_iterations_per_s=nv * info["iterations"] / (ms * 1e-3),
+                   sweep_ms=avg["sweep"], sweep_GBps=sweep_bytes / (avg["sweep"] * 1e-3) / 1e9,
+                   pcg_apply_ms=avg["pcg_apply"], vcycle_ms=avg["vcycle"], lowest_order_vcycle_ms=avg["lo_vcycle"],
+                   workspace_GiB=D.ws_bytes / 2 ** 30)
+        row["sweep_frac_hbm_peak"] = row["sweep_GBps"] / HBM_PEAK_GBS
+        out["runs"].append(row)
+        log(f"nlo {row}")
+        sols[prec] = x.cpu().numpy()
+        D.close()
+        H.close()
+    out["roofline"] = {"kernel": "k_dg1_sweep (general): residual + band forward/back substitution + update",
+                       "bound": "hbm", "achieved": out["runs"][0]["sweep_GBps"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": out["runs"][0]["sweep_frac_hbm_peak"], "traffic": None,
+                       "algorithmic_bytes_per_launch": 116 * nv, "launch_ms": out["runs"][0]["sweep_ms"]}
+    if not args.no_cpu_baseline:
+        oracle = native_oracle()
+        cn, bn = w.coefficients(), w.dg1_rhs()
+        t0 = time.perf_counter()
+        P = oracle.problem_for(w, cn)
+        G = oracle.DG1(P)
+        t1 = time.perf_counter()
+        x_or, info_or = G.pcg(bn, rtol=w.rtol, maxit=200)
+        t2 = time.perf_counter()
+        out["cpu_baseline"] = {"value": nv / (t2 - t1), "unit": "unknowns/s (FP64 solve)", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": f"the whole workload: setup {t1 - t0:.1f} s, FP64 solve "
+                               f"({info_or['iterations']} it) {t2 - t1:.1f} s; gcc -O3 -march=native -fopenmp, "
+                               f"{oracle.threads()} threads ({cpu_model()})"}
+        nrm = np.linalg.norm(x_or)
+        out["error_vs_oracle"] = {p: float(np.linalg.norm(sols[p] - x_or) / nrm) for p in sols}
+        out["oracle_iterations"] = info_or["iterations"]
+    print(json.dumps(out), flush=True)
+
+
 def all_configs(tp, torch, dev, args):
     """Time per solve (to each workload's rtol) for every workload, FP64 and
     mixed: setup, solve (median of 5 after 2 warm-ups), iterations, DOF
@@ -401,6 +482,9 @@ def main():
                          "(mg_fp32, mg_fp64, single_level; * matches all)")
     ap.add_argument("--robustness", action="store_true",
                     help="Courant-number and resolution study (single level vs multigrid variants)")
+    ap.add_argument("--nlo", action="store_true",
+                    help="the next-to-lowest-order (DG1) workload: banded LU line smoother, NLO V-cycle, CG")
+    ap.add_argument("--nlo-workload", default="nlo_dg1_256x256x64")
     ap.add_argument("--probe", action="store_true",
                     help="only run the finest-level FP32 sweep and a 1 GiB copy (for counter runs)")
     ap.add_argument("--cpu-baseline", action="store_true",
@@ -434,6 +518,9 @@ def main():
     if args.configs:
         all_configs(tp, torch, dev, args)
         return
+    if args.nlo:
+        nlo(tp, torch, dev, args)
+        return
     log(f"generating {w.name} ({w.dof} DOF)")
     c = torch.from_numpy(w.coefficients()).to(dev)
     b = torch.from_numpy(w.rhs()).to(dev)
@@ -454,6 +541,15 @@ def main():
         if record is not None:
             record.append(dict(info=info, info_adj=info_adj, sweep=H.profile_read(K_SWEEP),
                                vcycle=H.profile_read(K_VCYCLE), cg_apply=H.profile_read(K_PCG_APPLY)))
+            # per-level breakdown from separate V-cycles (events around every launch)
+            b32 = b.float()
+            H.vcycle(b32)
+            H.profile_enable(True, levels=True)
+            for _ in range(5):
+                H.vcycle(b32)
+            record[-1]["levels"] = [H.profile_read_level(l) for l in range(w.levels)]
+            record[-1]["levels_vcycle"] = H.profile_read(K_VCYCLE)
+            del b32
         H.close()
         return x, g
 
@@ -552,7 +648,11 @@ def main():
         },
         "vcycle_fp32": {"ms": vc_avg_s * 1e3, "model_bytes_per_dof": VCYCLE_WORDS * 4,
                         "model_GBps": vc_gbs, "frac_hbm_peak": vc_gbs / HBM_PEAK_GBS,
-                        "frac_of_copy": vc_gbs / copy_gbs},
+                        "frac_of_copy": vc_gbs / copy_gbs,
+                        # per V-cycle, the kernels on each level (finest first), from 5 separate
+                        # V-cycles timed with events around every launch, and those V-cycles' time
+                        "levels_ms": [lv[0] / max(r["levels_vcycle"][1], 1) for lv in r["levels"]],
+                        "levels_vcycle_ms": r["levels_vcycle"][0] / max(r["levels_vcycle"][1], 1)},
         "stream": {"copy_GBps": copy_gbs, "copy_frac_hbm_peak": copy_gbs / HBM_PEAK_GBS,
                    "sweep_frac_of_copy": achieved / copy_gbs},
         "roofline": {"kernel": "k_sweep<float> finest level (general sweep)", "bound": "hbm",

@@ -230,9 +230,11 @@ tpmg_status tpmg_level_coefficients(const tpmg_hierarchy *h, int32_t level, int3
 
 /*
  * Kernel timing with HIP events recorded on the launch stream around every
- * launch of one kernel class (for bandwidth accounting).  Enabling resets the
- * counters.  read synchronises the recorded events and returns the summed
- * duration and the launch count.
+ * launch of one kernel class (for bandwidth accounting).  enable: 0 off, 1 the
+ * kernel classes below, 2 also every launch on each V-cycle level
+ * (tpmg_profile_read_level; the extra events lengthen a V-cycle slightly).
+ * Enabling resets the counters.  read synchronises the recorded events and
+ * returns the summed duration and the launch count.
  */
 typedef enum {
     TPMG_K_SWEEP = 0,        /* line sweep, general form, finest level          */
@@ -242,11 +244,20 @@ typedef enum {
     TPMG_K_PCG_APPLY = 4,    /* CG direction update + operator apply            */
     TPMG_K_PCG_UPDATE = 5,   /* CG x / r update                                 */
     TPMG_K_VCYCLE = 6,       /* one whole V-cycle                               */
-    TPMG_K_COUNT = 7
+    TPMG_K_DG1_SWEEP = 7,    /* DG1 line sweep, general form (tpmg_dg1_*)       */
+    TPMG_K_DG1_PCG_APPLY = 8,/* DG1 CG direction update + operator apply        */
+    TPMG_K_DG1_VCYCLE = 9,   /* one whole DG1 (NLO) V-cycle                     */
+    TPMG_K_COUNT = 10
 } tpmg_kernel_class;
 tpmg_status tpmg_profile_enable(tpmg_hierarchy *h, int32_t enable);
 tpmg_status tpmg_profile_read(tpmg_hierarchy *h, int32_t kernel_class, double *total_ms,
                               int64_t *launches);
+/* The same for every kernel that runs on V-cycle level `level` (its sweeps,
+ * its residual + restriction, the prolongation sweep into it, the coarsest
+ * solve), per launch: the per-level breakdown of a V-cycle (the view of the
+ * paper's Tab. MultigridBreakdown).  Level-0 time inside the DG1 (NLO)
+ * V-cycle counts on level 0. */
+tpmg_status tpmg_profile_read_level(tpmg_hierarchy *h, int32_t level, double *total_ms, int64_t *launches);
 
 /*
  * Plain device copy dst <- src of `bytes` bytes (multiple of 16, 16-byte
@@ -313,6 +324,85 @@ tpmg_status tpmg_mixed_precondition(const tpmg_hierarchy *h, int32_t fp32, const
 tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *h, const double *b_dev, double *x_dev, void *workspace_dev,
                              size_t workspace_bytes, const tpmg_mixed_opts *opts, tpmg_solve_info *info,
                              void *stream);
+
+/*
+ * Next-to-lowest-order (NLO) pressure level on the finest grid (Tab.
+ * FiniteElements: DG_1 pressure, six unknowns per cell), its vertical line
+ * smoother by a banded LU that is factorised once and applied per sweep
+ * (Sec. 4.3.1: LAPACK dgbtrf at setup, dgbtrs per application), and the
+ * p-coarsening to the lowest-order level by the natural embedding of DG_0
+ * in DG_1 (Sec. 4.2.1); the lowest-order hierarchy of h is the rest of the
+ * multigrid hierarchy.
+ *
+ * OPERATOR (a reading: the paper assembles its NLO operator with finite
+ * element machinery it does not spell out).  Cell (i, j, k) has reference
+ * coordinates xi, eta, zeta in [-1, 1] and unknowns u_{3v+h},
+ *     u = sum_{v=0,1} sum_{h=0..2} u_{3v+h} l_v(zeta) psi_h(xi, eta),
+ * psi = (1, xi, eta), l_0 = (1 - zeta)/2, l_1 = (1 + zeta)/2 (bottom and top
+ * values of a linear function in the vertical).  With width 1 and height s_k,
+ *     (H1 u, w) = sum over cells of  s_k <u w>
+ *                 + 4 a_h s_k (c^x <u_xi w_xi> + c^y <u_eta w_eta>)
+ *                 + 4 a_z c^z / s_k <u_zeta w_zeta>
+ *               + sum over faces f of  w_f <[u] [w]>_f,
+ * <.> the mean over the reference cell or face, [.] the jump across f,
+ * w_f the lowest-order face weight (a_h s_k c_f east / north, a_z c_f /
+ * t_{k+1/2} upper), c^x = (c_E + c_W)/2, c^y = (c_N + c_S)/2 of the cell's
+ * own faces, c^z the mean of its vertical faces (the one face at the bottom
+ * and top cells).  Symmetric positive definite; for cellwise constants it
+ * is exactly the lowest-order operator (P^T H1 P = H_0).
+ *
+ * The column block H1_z (all couplings inside a column: cell terms, the
+ * self parts of the horizontal faces, the vertical faces) is banded with 5
+ * sub- and 5 super-diagonals in the row order r = 6 k + a; it is factorised
+ * without pivoting (SPD).  Smoother: u <- u + omega H1_z^{-1} (b - H1 u)
+ * with the hierarchy's omega.  Transfers: P1 e0 adds e0 to u_0 and u_3 (the
+ * bottom and top values of the constant mode); R1 = P1^T.  NLO V-cycle
+ * from a zero guess: nu_pre DG1 sweeps, b0 = R1 (b - H1 u), one lowest-order
+ * V-cycle of h on b0 (FP32 in a mixed hierarchy), u += P1 e0, nu_post DG1
+ * sweeps.
+ *
+ * LAYOUT: DG1 vectors are FP64 arrays (6, nz, n, n): unknown a of cell
+ * (i, j, k) at ((a nz + k) n + j) n + i.  Lowest-order vectors are level-major
+ * (nz, n, n).  The hierarchy must have nz >= 2 and be used level-major; its
+ * DG1 vectors must stay below 4 GiB (6 n^2 nz < 2^29) (TPMG_ERR_SHAPE).
+ *
+ * OWNERSHIP: the caller owns the DG1 workspace (tpmg_dg1_workspace_bytes,
+ * 256-byte aligned: band factors of 88 n^2 nz doubles, nine DG1 vectors,
+ * two lowest-order vectors); the handle aliases it and h.  Calls use the
+ * reduction buffers and coarse-level vectors of h: they must not overlap
+ * other calls on h.  Buffers of one call must not alias unless stated.
+ */
+typedef struct tpmg_dg1 tpmg_dg1;
+tpmg_status tpmg_dg1_workspace_bytes(const tpmg_hierarchy *h, size_t *bytes);
+/* Factorise every column block on the device (TPMG_ERR_NOT_SPD on a
+ * non-positive pivot).  Synchronises `stream`. */
+tpmg_status tpmg_dg1_setup(const tpmg_hierarchy *h, void *workspace_dev, size_t workspace_bytes, void *stream,
+                           tpmg_dg1 **out);
+/* y = H1 x (asynchronous). */
+tpmg_status tpmg_dg1_apply(const tpmg_dg1 *g, const double *x_dev, double *y_dev, void *stream);
+/* x = H1_z^{-1} r in every column: forward and back substitution with the
+ * band factors (the per-application dgbtrs of Sec. 4.3.1; asynchronous). */
+tpmg_status tpmg_dg1_line_solve(const tpmg_dg1 *g, const double *r_dev, double *x_dev, void *stream);
+/* u_out = u + omega H1_z^{-1} (b - H1 u); u = NULL means u = 0 (asynchronous). */
+tpmg_status tpmg_dg1_smooth(const tpmg_dg1 *g, const double *u_dev, const double *b_dev, double *u_out_dev,
+                            void *stream);
+/* b0 = R1 (b - H1 u), a lowest-order level-major vector (asynchronous). */
+tpmg_status tpmg_dg1_residual_restrict(const tpmg_dg1 *g, const double *u_dev, const double *b_dev,
+                                       double *b0_dev, void *stream);
+/* u += P1 e0, in place (e0 lowest-order level-major; asynchronous). */
+tpmg_status tpmg_dg1_prolong_add(const tpmg_dg1 *g, const double *e0_dev, double *u_dev, void *stream);
+/* z = V1 b, the NLO V-cycle from a zero guess (asynchronous). */
+tpmg_status tpmg_dg1_vcycle(const tpmg_dg1 *g, const double *b_dev, double *z_dev, void *stream);
+/* CG on H1 x = b from x = 0 with one NLO V-cycle per iteration (FP64 outer
+ * iteration; opts as for tpmg_solve, with x0_nonzero = 0 and omega_alt = 0
+ * required).  Same return values as tpmg_solve.  Synchronises `stream`. */
+tpmg_status tpmg_dg1_solve(const tpmg_dg1 *g, const double *b_dev, double *x_dev, const tpmg_solve_opts *opts,
+                           tpmg_solve_info *info, void *stream);
+/* Copy of the band factors, [col = j n + i][r][e] (n^2 x 6 nz x 11): L(r, r-5+e)
+ * for e < 5, U(r, r) for e = 5, U(r, r+e-5) for e > 5 (0 outside the matrix). */
+tpmg_status tpmg_dg1_factors(const tpmg_dg1 *g, double *f_dev, void *stream);
+/* Release the handle (not the workspace).  NULL is accepted. */
+tpmg_status tpmg_dg1_destroy(tpmg_dg1 *g);
 
 const char *tpmg_status_string(tpmg_status s);
 /* Last error text of a handle, or of the calling thread when h is NULL. */

@@ -18,7 +18,8 @@ OK, NOT_CONVERGED = 0, 1
 LEVEL_MAJOR, COLUMN_MAJOR = 0, 1
 FP64, MIXED = 0, 1
 COARSE_DIRECT, COARSE_SMOOTH = 0, 1
-K_SWEEP, K_SWEEP0, K_PROLSWEEP, K_RESTRICT, K_PCG_APPLY, K_PCG_UPDATE, K_VCYCLE = range(7)
+(K_SWEEP, K_SWEEP0, K_PROLSWEEP, K_RESTRICT, K_PCG_APPLY, K_PCG_UPDATE, K_VCYCLE, K_DG1_SWEEP, K_DG1_PCG_APPLY,
+ K_DG1_VCYCLE) = range(10)
 
 EXPORTS = [
     "tpmg_workspace_bytes", "tpmg_setup_hierarchy", "tpmg_level_n", "tpmg_apply_operator",
@@ -26,8 +27,10 @@ EXPORTS = [
     "tpmg_vcycle", "tpmg_solve", "tpmg_face_gradient", "tpmg_smooth", "tpmg_residual_restrict",
     "tpmg_prolong_smooth", "tpmg_coarse_solve", "tpmg_mixed_workspace_bytes", "tpmg_mixed_apply",
     "tpmg_mixed_precondition", "tpmg_mixed_solve", "tpmg_level_coefficients", "tpmg_profile_enable",
-    "tpmg_profile_read", "tpmg_bandwidth_probe", "tpmg_destroy", "tpmg_status_string",
-    "tpmg_last_error",
+    "tpmg_profile_read", "tpmg_profile_read_level", "tpmg_bandwidth_probe", "tpmg_destroy", "tpmg_status_string",
+    "tpmg_last_error", "tpmg_dg1_workspace_bytes", "tpmg_dg1_setup", "tpmg_dg1_apply", "tpmg_dg1_line_solve",
+    "tpmg_dg1_smooth", "tpmg_dg1_residual_restrict", "tpmg_dg1_prolong_add", "tpmg_dg1_vcycle", "tpmg_dg1_solve",
+    "tpmg_dg1_factors", "tpmg_dg1_destroy",
 ]
 
 
@@ -91,8 +94,18 @@ def lib():
         L.tpmg_level_coefficients.argtypes = [vp, i32, i32, vp, vp]
         L.tpmg_profile_enable.argtypes = [vp, i32]
         L.tpmg_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.tpmg_profile_read_level.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tpmg_bandwidth_probe.argtypes = [vp, vp, C.c_size_t, vp]
         L.tpmg_destroy.argtypes = [vp]
+        L.tpmg_dg1_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.tpmg_dg1_setup.argtypes = [vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        for name in ("tpmg_dg1_apply", "tpmg_dg1_line_solve", "tpmg_dg1_vcycle", "tpmg_dg1_prolong_add"):
+            getattr(L, name).argtypes = [vp, vp, vp, vp]
+        L.tpmg_dg1_smooth.argtypes = [vp, vp, vp, vp, vp]
+        L.tpmg_dg1_residual_restrict.argtypes = [vp, vp, vp, vp, vp]
+        L.tpmg_dg1_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.tpmg_dg1_factors.argtypes = [vp, vp, vp]
+        L.tpmg_dg1_destroy.argtypes = [vp]
         L.tpmg_status_string.argtypes = [st]
         L.tpmg_status_string.restype = C.c_char_p
         L.tpmg_last_error.argtypes = [vp]
@@ -382,14 +395,151 @@ class Hierarchy:
         return x, res
 
     # -- profiling ------------------------------------------------------------------
-    def profile_enable(self, on: bool = True):
-        _check(lib().tpmg_profile_enable(self.handle, int(on)), "tpmg_profile_enable", self.handle)
+    def profile_enable(self, on: bool = True, levels: bool = False):
+        """Event timers: kernel classes, and with levels=True every launch per
+        V-cycle level too."""
+        mode = (2 if levels else 1) if on else 0
+        _check(lib().tpmg_profile_enable(self.handle, mode), "tpmg_profile_enable", self.handle)
 
     def profile_read(self, kernel_class: int):
         ms, n = C.c_double(0), C.c_int64(0)
         _check(lib().tpmg_profile_read(self.handle, kernel_class, C.byref(ms), C.byref(n)),
                "tpmg_profile_read", self.handle)
         return ms.value, n.value
+
+    def profile_read_level(self, level: int):
+        """(total ms, launches) of the kernels on one V-cycle level."""
+        ms, n = C.c_double(0), C.c_int64(0)
+        _check(lib().tpmg_profile_read_level(self.handle, level, C.byref(ms), C.byref(n)),
+               "tpmg_profile_read_level", self.handle)
+        return ms.value, n.value
+
+
+class DG1Level:
+    """The next-to-lowest-order (DG1) pressure level on the finest grid of a
+    level-major hierarchy (tpmg_dg1_*): the band LU of every column block is
+    formed at construction; the operator, line solve, sweeps, p-transfers,
+    NLO V-cycle and CG then run on it.  DG1 arrays are contiguous float64 CUDA
+    tensors of shape (6, nz, n, n), unknown a = 3 v + h of cell (i, j, k);
+    lowest-order arrays are (nz, n, n).  Calls must not overlap other calls
+    on the same hierarchy."""
+
+    def __init__(self, H: Hierarchy):
+        if H.layout != LEVEL_MAJOR:
+            raise ValueError("the DG1 level needs a level-major hierarchy")
+        self.H, self.n, self.nz, self.device = H, H.n, H.nz, H.device
+        nb = C.c_size_t(0)
+        _check(lib().tpmg_dg1_workspace_bytes(H.handle, C.byref(nb)), "tpmg_dg1_workspace_bytes", H.handle)
+        self.ws_bytes = nb.value
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=H.device)
+        g = C.c_void_p()
+        _check(lib().tpmg_dg1_setup(H.handle, _ptr(self.workspace), self.ws_bytes, _stream(H.device),
+                                    C.byref(g)), "tpmg_dg1_setup", H.handle)
+        self._g = g
+
+    def close(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            lib().tpmg_dg1_destroy(g)
+        self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._g is None:
+            raise RuntimeError("DG1 level is closed")
+        return self._g
+
+    @property
+    def shape(self):
+        return (6, self.nz, self.n, self.n)
+
+    def _vec(self, t: torch.Tensor, name: str, shape=None):
+        shape = self.shape if shape is None else shape
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and tuple(t.shape) == shape):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+        return t
+
+    def _unary(self, fn: str, x: torch.Tensor) -> torch.Tensor:
+        self._vec(x, "x")
+        y = torch.empty_like(x)
+        _check(getattr(lib(), fn)(self.handle, _ptr(x), _ptr(y), _stream(self.device)), fn, self.H.handle)
+        return y
+
+    def apply(self, x: torch.Tensor) -> torch.Tensor:
+        """y = H1 x."""
+        return self._unary("tpmg_dg1_apply", x)
+
+    def line_solve(self, r: torch.Tensor) -> torch.Tensor:
+        """x = H1_z^{-1} r in every column (forward / back substitution)."""
+        return self._unary("tpmg_dg1_line_solve", r)
+
+    def vcycle(self, b: torch.Tensor) -> torch.Tensor:
+        """z = V1 b, the NLO V-cycle from a zero guess."""
+        return self._unary("tpmg_dg1_vcycle", b)
+
+    def smooth(self, b: torch.Tensor, u: torch.Tensor | None = None) -> torch.Tensor:
+        self._vec(b, "b")
+        if u is not None:
+            self._vec(u, "u")
+        out = torch.empty_like(b)
+        _check(lib().tpmg_dg1_smooth(self.handle, _ptr(u) if u is not None else None, _ptr(b), _ptr(out),
+                                     _stream(self.device)), "tpmg_dg1_smooth", self.H.handle)
+        return out
+
+    def residual_restrict(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        """b0 = R1 (b - H1 u) on the lowest-order level 0."""
+        self._vec(u, "u")
+        self._vec(b, "b")
+        out = torch.empty((self.nz, self.n, self.n), dtype=torch.float64, device=self.device)
+        _check(lib().tpmg_dg1_residual_restrict(self.handle, _ptr(u), _ptr(b), _ptr(out), _stream(self.device)),
+               "tpmg_dg1_residual_restrict", self.H.handle)
+        return out
+
+    def prolong_add(self, e0: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+        """u + P1 e0 (u is not modified; a new tensor is returned)."""
+        self._vec(e0, "e0", (self.nz, self.n, self.n))
+        out = self._vec(u, "u").clone()
+        _check(lib().tpmg_dg1_prolong_add(self.handle, _ptr(e0), _ptr(out), _stream(self.device)),
+               "tpmg_dg1_prolong_add", self.H.handle)
+        return out
+
+    def factors(self) -> torch.Tensor:
+        """Band factors, shape (n, n, 6 nz, 11): [j, i, row r = 6 k + a, entry]
+        with L(r, r-5..r-1), U(r, r), U(r, r+1..r+5)."""
+        out = torch.empty((self.n, self.n, 6 * self.nz, 11), dtype=torch.float64, device=self.device)
+        _check(lib().tpmg_dg1_factors(self.handle, _ptr(out), _stream(self.device)), "tpmg_dg1_factors",
+               self.H.handle)
+        return out
+
+    def solve(self, b: torch.Tensor, rtol: float = 1e-8, maxit: int = 100, flexible: bool | None = None,
+              history: bool = False):
+        """CG on H1 x = b from x = 0, one NLO V-cycle per iteration.
+        Returns (x, info dict)."""
+        import numpy as np
+        self._vec(b, "b")
+        x = torch.empty_like(b)
+        opts = SolveOpts()
+        opts.rtol, opts.maxit = float(rtol), int(maxit)
+        opts.x0_nonzero = 0
+        opts.flexible = int(self.H.mixed if flexible is None else bool(flexible))
+        opts.omega_alt = 0.0
+        hist = np.zeros(maxit + 1) if history else None
+        opts.history = hist.ctypes.data_as(C.c_void_p) if hist is not None else None
+        info = SolveInfo()
+        st = lib().tpmg_dg1_solve(self.handle, _ptr(b), _ptr(x), C.byref(opts), C.byref(info),
+                                  _stream(self.device))
+        _check(st, "tpmg_dg1_solve", self.H.handle, ok=(OK, NOT_CONVERGED))
+        res = dict(iterations=info.iterations, converged=bool(info.converged), rel_residual=info.rel_residual,
+                   true_rel_residual=info.true_rel_residual, status=st)
+        if hist is not None:
+            res["history"] = hist[: info.iterations + 1].copy()
+        return x, res
 
 
 def bandwidth_probe(dst: torch.Tensor, src: torch.Tensor):

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtpmg.so")
 SOURCES = [os.path.join(HERE, "csrc", "tpmg_kernels.hip"), os.path.join(HERE, "csrc", "tpmg_mixed.hip"),
+           os.path.join(HERE, "csrc", "tpmg_dg1.hip"),
            os.path.join(HERE, "csrc", "tpmg_host.hip")]
 ARCH = os.environ.get("TPMG_OFFLOAD_ARCH", "gfx950")
 

@@ -59,8 +59,8 @@ struct tpmg_hierarchy {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     std::string err;
-    bool prof = false;
-    EventPool pools[TPMG_K_COUNT];
+    bool prof = false, prof_levels = false;
+    EventPool pools[TPMG_K_COUNT + TPMG_MAX_LEVELS];  // kernel classes, then one per level
     // damping of the sweeps of the next V-cycle: d.omega, except inside a
     // solve whose options make the preconditioner vary between iterations
     double omega_run = 0.0;
@@ -224,6 +224,10 @@ const LevelBufs &bufs(const tpmg_hierarchy *h, int l)
 
 // ---- profiling --------------------------------------------------------------
 
+// Event pool of the kernels that run on V-cycle level l.
+constexpr int kLevelPool = TPMG_K_COUNT;
+constexpr int kPools = TPMG_K_COUNT + TPMG_MAX_LEVELS;
+
 struct Timed {
     tpmg_hierarchy *h;
     int cls;
@@ -231,7 +235,7 @@ struct Timed {
     bool on;
     Timed(const tpmg_hierarchy *hc, int c, hipStream_t st) : h(const_cast<tpmg_hierarchy *>(hc)), cls(c), s(st)
     {
-        on = h->prof && cls >= 0;
+        on = h->prof && cls >= 0 && (cls < kLevelPool || h->prof_levels);
         if (!on) return;
         EventPool &P = h->pools[cls];
         if (P.used == (int)P.start.size()) {
@@ -264,7 +268,7 @@ tpmg_status sweep(const tpmg_hierarchy *h, int l, int mode, const T *u, const T 
 {
     int cls = -1;
     if (l == 0) cls = mode == SWEEP_ZERO ? TPMG_K_SWEEP0 : (mode == SWEEP_GENERAL ? TPMG_K_SWEEP : TPMG_K_PROLSWEEP);
-    Timed t(h, cls, s);
+    Timed t(h, cls, s), tl(h, kLevelPool + l, s);
     HIP_TRY(const_cast<tpmg_hierarchy *>(h),
             launch_sweep<T>(level_view<T>(h, l), mode, u, b, out, ec, (T)h->omega_run, s));
     return TPMG_OK;
@@ -277,6 +281,7 @@ tpmg_status coarse_solve(const tpmg_hierarchy *h, const T *b, T *out, hipStream_
     tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
     if (h->d.coarse == TPMG_COARSE_DIRECT) {
         const T *ainv = (sizeof(T) == 8) ? (const T *)h->ainv64 : (const T *)h->ainv32;
+        Timed tl(h, kLevelPool + l, s);
         HIP_TRY(hm, launch_coarse_gemv<T>(ainv, h->m_coarse, b, out, s));
         return TPMG_OK;
     }
@@ -309,7 +314,7 @@ tpmg_status vcycle_level(const tpmg_hierarchy *h, int l, const T *b, T *out, hip
         std::swap(cur, other);
     }
     {
-        Timed t(h, l == 0 ? TPMG_K_RESTRICT : -1, s);  // M2
+        Timed t(h, l == 0 ? TPMG_K_RESTRICT : -1, s), tl(h, kLevelPool + l, s);  // M2
         HIP_TRY(hm, launch_resid_restrict<T>(level_view<T>(h, l), cur, b, (T *)C.b, s));
     }
     if ((st = vcycle_level<T>(h, l + 1, (const T *)C.b, (T *)C.E, s)) != TPMG_OK) return st;  // M3
@@ -526,6 +531,22 @@ tpmg_status coarse_solve_impl(const tpmg_hierarchy *h, const void *b, void *u, h
     if ((st = stage_in(h, b, bs, l, sizeof(T), s)) != TPMG_OK) return st;
     if ((st = coarse_solve<T>(h, bs, os, s)) != TPMG_OK) return st;
     return stage_out(h, os, u, l, sizeof(T), s);
+}
+
+// Sum of the recorded event pairs of one pool (synchronises them).
+tpmg_status read_pool(tpmg_hierarchy *h, int pool, double *total_ms, int64_t *launches)
+{
+    EventPool &P = h->pools[pool];
+    for (int i = 0; i < P.used; ++i) {
+        float ms = 0;
+        HIP_TRY(h, hipEventSynchronize(P.stop[i]));
+        HIP_TRY(h, hipEventElapsedTime(&ms, P.start[i], P.stop[i]));
+        P.acc_ms += ms;
+    }
+    P.used = 0;
+    *total_ms = P.acc_ms;
+    *launches = P.launches;
+    return TPMG_OK;
 }
 
 // ---- staging memory of tpmg_apply_operator_static -------------------------------
@@ -1025,7 +1046,8 @@ tpmg_status tpmg_profile_enable(tpmg_hierarchy *h, int32_t enable)
 {
     tpmg_status st;
     if ((st = check_handle(h)) != TPMG_OK) return st;
-    for (int c = 0; c < TPMG_K_COUNT; ++c) {
+    if (enable < 0 || enable > 2) return fail(h, TPMG_ERR_INVALID_ARG, "enable must be 0, 1 or 2");
+    for (int c = 0; c < kPools; ++c) {
         EventPool &P = h->pools[c];
         if (enable && P.start.empty()) {
             P.start.resize(512);
@@ -1040,6 +1062,7 @@ tpmg_status tpmg_profile_enable(tpmg_hierarchy *h, int32_t enable)
         P.launches = 0;
     }
     h->prof = enable != 0;
+    h->prof_levels = enable == 2;
     return TPMG_OK;
 }
 
@@ -1049,17 +1072,16 @@ tpmg_status tpmg_profile_read(tpmg_hierarchy *h, int32_t kernel_class, double *t
     if ((st = check_handle(h)) != TPMG_OK) return st;
     if (kernel_class < 0 || kernel_class >= TPMG_K_COUNT || !total_ms || !launches)
         return fail(h, TPMG_ERR_INVALID_ARG, "bad profile query");
-    EventPool &P = h->pools[kernel_class];
-    for (int i = 0; i < P.used; ++i) {
-        float ms = 0;
-        HIP_TRY(h, hipEventSynchronize(P.stop[i]));
-        HIP_TRY(h, hipEventElapsedTime(&ms, P.start[i], P.stop[i]));
-        P.acc_ms += ms;
-    }
-    P.used = 0;
-    *total_ms = P.acc_ms;
-    *launches = P.launches;
-    return TPMG_OK;
+    return read_pool(h, kernel_class, total_ms, launches);
+}
+
+tpmg_status tpmg_profile_read_level(tpmg_hierarchy *h, int32_t level, double *total_ms, int64_t *launches)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    if (level < 0 || level >= h->L || !total_ms || !launches)
+        return fail(h, TPMG_ERR_INVALID_ARG, "bad profile query");
+    return read_pool(h, kLevelPool + level, total_ms, launches);
 }
 
 tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t bytes, void *stream)
@@ -1426,7 +1448,7 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *hc, const double *b_dev, doub
 tpmg_status tpmg_destroy(tpmg_hierarchy *h)
 {
     if (!h) return TPMG_OK;
-    for (int c = 0; c < TPMG_K_COUNT; ++c) {
+    for (int c = 0; c < kPools; ++c) {
         for (hipEvent_t e : h->pools[c].start) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->pools[c].stop) (void)hipEventDestroy(e);
     }
@@ -1454,6 +1476,383 @@ const char *tpmg_last_error(const tpmg_hierarchy *h)
 {
     if (h) return h->err.c_str();
     return g_last_error.c_str();
+}
+
+}  // extern "C"
+
+// =============================================================================
+// Next-to-lowest-order (DG1) pressure level on the finest grid: banded column
+// factors, operator, sweeps, p-transfers, the NLO V-cycle and its CG.
+// =============================================================================
+
+struct tpmg_dg1 {
+    tpmg_hierarchy *h = nullptr;
+    Dg1Level G{};
+    size_t nv = 0;                     // 6 n^2 nz unknowns
+    double *fac = nullptr, *tab = nullptr;
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    double *A = nullptr, *B = nullptr;  // sweep vectors of the V-cycle and the component calls
+    double *b0 = nullptr, *e0 = nullptr;  // lowest-order level-0 vectors (FP64 correction)
+};
+
+namespace {
+
+constexpr int kDg1Nf = 11;  // band entries per factor row
+
+// Carve a DG1 workspace; with g == nullptr only the size is computed.
+size_t plan_dg1(const tpmg_hierarchy *h, tpmg_dg1 *g, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> double * {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        double *p = g ? (double *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t plane = (size_t)h->l64[0].plane, nz = (size_t)h->nz;
+    const size_t nv = plane * 6 * nz, ncell = plane * nz;
+    double *fac = take(nv * kDg1Nf * 8);
+    double *tab = take(5 * nz * 8);
+    double *v[9];
+    for (int i = 0; i < 9; ++i) v[i] = take(nv * 8);
+    double *b0 = take(ncell * 8), *e0 = take(ncell * 8);
+    if (g) {
+        g->nv = nv;
+        g->fac = fac;
+        g->tab = tab;
+        g->b = v[0];
+        g->x = v[1];
+        g->r = v[2];
+        g->z = v[3];
+        g->p0 = v[4];
+        g->p1 = v[5];
+        g->q = v[6];
+        g->A = v[7];
+        g->B = v[8];
+        g->b0 = b0;
+        g->e0 = e0;
+    }
+    return (off + kAlign - 1) / kAlign * kAlign;
+}
+
+tpmg_status check_dg1_shape(const tpmg_hierarchy *h)
+{
+    tpmg_hierarchy *hm = const_cast<tpmg_hierarchy *>(h);
+    if (h->nz < 2) return fail(hm, TPMG_ERR_SHAPE, "the DG1 level needs nz >= 2");
+    const size_t plane = (size_t)h->l64[0].plane, rows = 6 * (size_t)h->nz;
+    if (plane * rows * 8 >= ((size_t)1 << 32))
+        return fail(hm, TPMG_ERR_SHAPE, "DG1 vectors would reach 4 GiB (kernels use 32-bit byte offsets)");
+    if ((plane & 63) != 0 && plane * rows * kDg1Nf * 8 >= ((size_t)1 << 32))
+        return fail(hm, TPMG_ERR_SHAPE, "band factors of a plane that is not a multiple of 64 would reach 4 GiB");
+    return TPMG_OK;
+}
+
+tpmg_status check_dg1(const tpmg_dg1 *g)
+{
+    if (!g || !g->h) return fail(nullptr, TPMG_ERR_INVALID_ARG, "DG1 handle is NULL");
+    return TPMG_OK;
+}
+
+// caller's (6, nz, n, n) level-major DG1 array <-> the tiled storage
+tpmg_status dg1_in(const tpmg_dg1 *g, const double *src, double *dst, double *dst2, hipStream_t s)
+{
+    HIP_TRY(g->h, launch_cells_in(src, TPMG_LAYOUT_LEVEL_MAJOR, dst, dst2, g->G.plane, 6 * g->G.nz, 8, s));
+    return TPMG_OK;
+}
+
+tpmg_status dg1_out(const tpmg_dg1 *g, const double *src, double *dst, hipStream_t s)
+{
+    HIP_TRY(g->h, launch_cells_out(src, dst, TPMG_LAYOUT_LEVEL_MAJOR, g->G.plane, 6 * g->G.nz, 8, s));
+    return TPMG_OK;
+}
+
+tpmg_status dg1_sweep(const tpmg_dg1 *g, int mode, const double *u, const double *b, double *out, hipStream_t s)
+{
+    Timed t(g->h, mode == DG1_SWEEP_GENERAL ? TPMG_K_DG1_SWEEP : -1, s);
+    HIP_TRY(g->h, launch_dg1_sweep(g->G, g->fac, mode, u, b, out, g->h->d.omega, s));
+    return TPMG_OK;
+}
+
+// out = V1 b (zero initial guess): nu_pre DG1 sweeps, p-restriction of the
+// residual to the lowest-order level 0, one lowest-order V-cycle there (in the
+// hierarchy's precision), the correction added by the embedding, nu_post DG1
+// sweeps (Sec. 4.2.1: the first coarsening step is DG1 -> DG0).  b and out
+// must not be A or B.
+tpmg_status dg1_vcycle(const tpmg_dg1 *g, const double *b, double *out, hipStream_t s)
+{
+    tpmg_hierarchy *h = g->h;
+    Timed t(h, TPMG_K_DG1_VCYCLE, s);
+    double *cur = g->A, *other = g->B;
+    tpmg_status st;
+    if ((st = dg1_sweep(g, DG1_SWEEP_ZERO, nullptr, b, cur, s)) != TPMG_OK) return st;
+    for (int i = 1; i < h->d.nu_pre; ++i) {
+        if ((st = dg1_sweep(g, DG1_SWEEP_GENERAL, cur, b, other, s)) != TPMG_OK) return st;
+        std::swap(cur, other);
+    }
+    if (h->mixed) {
+        HIP_TRY(h, launch_dg1_resid_restrict(g->G, cur, b, h->r32, 1, s));
+        if ((st = vcycle<float>(h, h->r32, h->z32, s)) != TPMG_OK) return st;
+        HIP_TRY(h, launch_dg1_prolong(g->G, h->z32, 1, cur, s));
+    } else {
+        HIP_TRY(h, launch_dg1_resid_restrict(g->G, cur, b, g->b0, 0, s));
+        if ((st = vcycle<double>(h, g->b0, g->e0, s)) != TPMG_OK) return st;
+        HIP_TRY(h, launch_dg1_prolong(g->G, g->e0, 0, cur, s));
+    }
+    const double *src = cur;
+    for (int i = 0; i < h->d.nu_post; ++i) {
+        double *dst = (i == h->d.nu_post - 1) ? out : ((i % 2 == 0) ? other : cur);
+        if ((st = dg1_sweep(g, DG1_SWEEP_GENERAL, src, b, dst, s)) != TPMG_OK) return st;
+        src = dst;
+    }
+    return TPMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tpmg_status tpmg_dg1_workspace_bytes(const tpmg_hierarchy *h, size_t *bytes)
+{
+    tpmg_status st;
+    if ((st = check_handle(h)) != TPMG_OK) return st;
+    if (!bytes) return fail(const_cast<tpmg_hierarchy *>(h), TPMG_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_dg1_shape(h)) != TPMG_OK) return st;
+    *bytes = plan_dg1(h, nullptr, nullptr);
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_dg1_setup(const tpmg_hierarchy *hc, void *workspace_dev, size_t workspace_bytes, void *stream,
+                           tpmg_dg1 **out)
+{
+    tpmg_status st;
+    if ((st = check_handle(hc)) != TPMG_OK) return st;
+    tpmg_hierarchy *h = const_cast<tpmg_hierarchy *>(hc);
+    if (!out) return fail(h, TPMG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if ((st = check_dg1_shape(h)) != TPMG_OK) return st;
+    const size_t need = plan_dg1(h, nullptr, nullptr);
+    if (!workspace_dev || workspace_bytes < need || ((uintptr_t)workspace_dev % kAlign) != 0)
+        return fail(h, TPMG_ERR_WORKSPACE, "DG1 workspace missing, too small or not 256-byte aligned");
+    hipStream_t s = as_stream(stream);
+    tpmg_dg1 *g = new tpmg_dg1();
+    g->h = h;
+    plan_dg1(h, g, (char *)workspace_dev);
+    const int nz = h->nz;
+    g->G.n = h->l64[0].n;
+    g->G.nz = nz;
+    g->G.plane = h->l64[0].plane;
+    g->G.c = (const double *)h->l64[0].c;
+    g->G.tab = g->tab;
+    // per-k scalars of the finest level: s_k, a_h s_k, 4 a_h s_k, 4 a_z / s_k, a_z / t_{k+1/2}
+    std::vector<double> sk(nz, 1.0), tk(nz, 1.0), tab(5 * (size_t)nz, 0.0);
+    {
+        double mean = 0.0;
+        for (int k = 0; k < nz; ++k) mean += h->dz.empty() ? 1.0 : h->dz[k];
+        mean /= nz;
+        for (int k = 0; k < nz; ++k) sk[k] = (h->dz.empty() ? 1.0 : h->dz[k]) / mean;
+        for (int k = 0; k + 1 < nz; ++k) tk[k] = 0.5 * (sk[k] + sk[k + 1]);
+    }
+    for (int k = 0; k < nz; ++k) {
+        tab[k] = sk[k];
+        tab[nz + k] = h->d.a_h * sk[k];
+        tab[2 * nz + k] = 4.0 * h->d.a_h * sk[k];
+        tab[3 * nz + k] = 4.0 * h->d.a_z / sk[k];
+        tab[4 * nz + k] = (k + 1 < nz) ? h->d.a_z / tk[k] : 0.0;
+    }
+    hipError_t e;
+    int bad = 0;
+    if ((e = hipMemcpyAsync(g->tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_fill((double *)h->bad, 0.0, 1, s)) != hipSuccess ||
+        (e = launch_dg1_factor(g->G, g->fac, h->bad, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        delete g;
+        return hip_fail(h, e, "DG1 setup");
+    }
+    if (bad) {
+        delete g;
+        return fail(h, TPMG_ERR_NOT_SPD, std::to_string(bad) + " non-positive pivot(s) in the DG1 column factors");
+    }
+    *out = g;
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_dg1_apply(const tpmg_dg1 *g, const double *x_dev, double *y_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {x_dev, y_dev})) != TPMG_OK) return st;
+    hipStream_t s = as_stream(stream);
+    if ((st = dg1_in(g, x_dev, g->A, nullptr, s)) != TPMG_OK) return st;
+    HIP_TRY(g->h, launch_dg1_apply(g->G, g->A, g->B, s));
+    return dg1_out(g, g->B, y_dev, s);
+}
+
+tpmg_status tpmg_dg1_line_solve(const tpmg_dg1 *g, const double *r_dev, double *x_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {r_dev, x_dev})) != TPMG_OK) return st;
+    hipStream_t s = as_stream(stream);
+    if ((st = dg1_in(g, r_dev, g->A, nullptr, s)) != TPMG_OK) return st;
+    if ((st = dg1_sweep(g, DG1_SWEEP_SOLVE, nullptr, g->A, g->B, s)) != TPMG_OK) return st;
+    return dg1_out(g, g->B, x_dev, s);
+}
+
+tpmg_status tpmg_dg1_smooth(const tpmg_dg1 *g, const double *u_dev, const double *b_dev, double *u_out_dev,
+                            void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {b_dev, u_out_dev})) != TPMG_OK) return st;
+    if (u_dev && (st = check_ptrs(g->h, {u_dev})) != TPMG_OK) return st;
+    hipStream_t s = as_stream(stream);
+    if (u_dev && (st = dg1_in(g, u_dev, g->A, nullptr, s)) != TPMG_OK) return st;
+    if ((st = dg1_in(g, b_dev, g->b, nullptr, s)) != TPMG_OK) return st;
+    if ((st = dg1_sweep(g, u_dev ? DG1_SWEEP_GENERAL : DG1_SWEEP_ZERO, u_dev ? g->A : nullptr, g->b, g->B, s)) !=
+        TPMG_OK)
+        return st;
+    return dg1_out(g, g->B, u_out_dev, s);
+}
+
+tpmg_status tpmg_dg1_residual_restrict(const tpmg_dg1 *g, const double *u_dev, const double *b_dev, double *b0_dev,
+                                       void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {u_dev, b_dev, b0_dev})) != TPMG_OK) return st;
+    hipStream_t s = as_stream(stream);
+    if ((st = dg1_in(g, u_dev, g->A, nullptr, s)) != TPMG_OK || (st = dg1_in(g, b_dev, g->b, nullptr, s)) != TPMG_OK)
+        return st;
+    HIP_TRY(g->h, launch_dg1_resid_restrict(g->G, g->A, g->b, g->b0, 0, s));
+    HIP_TRY(g->h, launch_cells_out(g->b0, b0_dev, TPMG_LAYOUT_LEVEL_MAJOR, g->G.plane, g->G.nz, 8, s));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_dg1_prolong_add(const tpmg_dg1 *g, const double *e0_dev, double *u_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {e0_dev, u_dev})) != TPMG_OK) return st;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(g->h, launch_cells_in(e0_dev, TPMG_LAYOUT_LEVEL_MAJOR, g->e0, nullptr, g->G.plane, g->G.nz, 8, s));
+    if ((st = dg1_in(g, u_dev, g->A, nullptr, s)) != TPMG_OK) return st;
+    HIP_TRY(g->h, launch_dg1_prolong(g->G, g->e0, 0, g->A, s));
+    return dg1_out(g, g->A, u_dev, s);
+}
+
+tpmg_status tpmg_dg1_vcycle(const tpmg_dg1 *g, const double *b_dev, double *z_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {b_dev, z_dev})) != TPMG_OK) return st;
+    if ((const void *)b_dev == (const void *)z_dev) return fail(g->h, TPMG_ERR_INVALID_ARG, "b and z must not alias");
+    hipStream_t s = as_stream(stream);
+    if ((st = dg1_in(g, b_dev, g->b, nullptr, s)) != TPMG_OK) return st;
+    if ((st = dg1_vcycle(g, g->b, g->z, s)) != TPMG_OK) return st;
+    return dg1_out(g, g->z, z_dev, s);
+}
+
+tpmg_status tpmg_dg1_solve(const tpmg_dg1 *gc, const double *b_dev, double *x_dev, const tpmg_solve_opts *opts,
+                           tpmg_solve_info *info, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(gc)) != TPMG_OK) return st;
+    tpmg_dg1 *g = const_cast<tpmg_dg1 *>(gc);
+    tpmg_hierarchy *h = g->h;
+    if ((st = check_ptrs(h, {b_dev, x_dev})) != TPMG_OK) return st;
+    if (!opts) return fail(h, TPMG_ERR_INVALID_ARG, "opts is NULL");
+    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->flexible != 0 && opts->flexible != 1) ||
+        opts->x0_nonzero != 0 || opts->omega_alt != 0.0)
+        return fail(h, TPMG_ERR_INVALID_ARG, "bad DG1 solve options (x0_nonzero and omega_alt must be 0)");
+    if ((const void *)b_dev == (const void *)x_dev) return fail(h, TPMG_ERR_INVALID_ARG, "b and x must not alias");
+    hipStream_t s = as_stream(stream);
+    const size_t n = g->nv;
+    const int flex = opts->flexible;
+    double *b = g->b, *x = g->x;
+    int G = 0;
+    // b in storage order, r = b, x = 0 (written by the first update)
+    if ((st = dg1_in(g, b_dev, b, g->r, s)) != TPMG_OK) return st;
+    HIP_TRY(h, launch_fill((double *)h->sc, 0.0, sizeof(Scalars) / sizeof(double), s));
+    HIP_TRY(h, launch_dot(n, b, b, nullptr, h->partials, &G, s));
+    if ((st = finalize(h, G, 1, ST_BB, 0, s)) != TPMG_OK) return st;
+    if ((st = finalize(h, G, 1, ST_RR, 0, s)) != TPMG_OK) return st;
+    if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+    const double bnorm = std::sqrt(h->sc_host->bb);
+    double rnorm = std::sqrt(h->sc_host->rr);
+    double rel = bnorm > 0 ? rnorm / bnorm : 0.0;
+    if (opts->history) opts->history[0] = rel;
+    int it = 0;
+    bool converged = false, x_unset = true;
+    tpmg_status result = TPMG_NOT_CONVERGED;
+    if (!std::isfinite(bnorm)) {
+        result = TPMG_ERR_BREAKDOWN;
+        fail(h, result, "non-finite right-hand side");
+    } else if (bnorm == 0.0) {
+        converged = true;
+        result = TPMG_OK;
+    } else {
+        if ((st = dg1_vcycle(g, g->r, g->z, s)) != TPMG_OK) return st;
+        HIP_TRY(h, launch_dot(n, g->r, g->z, nullptr, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_RZ_FIRST, flex, s)) != TPMG_OK) return st;
+        double *pold = g->p1, *pnew = g->p0;
+        for (it = 1; it <= opts->maxit; ++it) {
+            {
+                Timed t(h, TPMG_K_DG1_PCG_APPLY, s);
+                HIP_TRY(h, launch_dg1_pcg_apply(g->G, g->z, pold, pnew, g->q, h->sc, it == 1, h->partials, &G, s));
+            }
+            if ((st = finalize(h, G, 1, ST_PQ, flex, s)) != TPMG_OK) return st;
+            HIP_TRY(h, launch_pcg_update(n, x, pnew, g->r, g->q, nullptr, h->sc, h->partials, x_unset ? 1 : 0, &G, s));
+            x_unset = false;
+            if ((st = finalize(h, G, 1, ST_RR, flex, s)) != TPMG_OK) return st;
+            if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+            if (h->sc_host->breakdown) {
+                result = TPMG_ERR_BREAKDOWN;
+                fail(h, result, "CG breakdown: (p, Hp) not positive or non-finite scalars");
+                break;
+            }
+            rnorm = std::sqrt(h->sc_host->rr);
+            rel = rnorm / bnorm;
+            if (opts->history) opts->history[it] = rel;
+            if (!std::isfinite(rnorm)) {
+                result = TPMG_ERR_BREAKDOWN;
+                fail(h, result, "non-finite residual");
+                break;
+            }
+            if (rnorm <= opts->rtol * bnorm) {
+                converged = true;
+                result = TPMG_OK;
+                break;
+            }
+            if (it == opts->maxit) break;
+            if ((st = dg1_vcycle(g, g->r, g->z, s)) != TPMG_OK) return st;
+            HIP_TRY(h, launch_dot(n, g->r, g->z, nullptr, h->partials, &G, s, flex ? g->q : nullptr));
+            if ((st = finalize(h, G, flex ? 2 : 1, ST_RZ, flex, s)) != TPMG_OK) return st;
+            std::swap(pold, pnew);
+        }
+        if (it > opts->maxit) it = opts->maxit;
+    }
+    if (x_unset) HIP_TRY(h, launch_fill(x, 0.0, n, s));
+    if (info) {
+        HIP_TRY(h, launch_dg1_residual(g->G, x, b, nullptr, h->partials, &G, s));
+        if ((st = finalize(h, G, 1, ST_TT, 0, s)) != TPMG_OK) return st;
+        if ((st = read_scalars(h, s)) != TPMG_OK) return st;
+        info->iterations = it;
+        info->converged = converged ? 1 : 0;
+        info->rel_residual = rel;
+        info->true_rel_residual = bnorm > 0 ? std::sqrt(h->sc_host->tt) / bnorm : 0.0;
+    }
+    if ((st = dg1_out(g, x, x_dev, s)) != TPMG_OK) return st;
+    HIP_TRY(h, hipStreamSynchronize(s));
+    return result;
+}
+
+tpmg_status tpmg_dg1_factors(const tpmg_dg1 *g, double *f_dev, void *stream)
+{
+    tpmg_status st;
+    if ((st = check_dg1(g)) != TPMG_OK || (st = check_ptrs(g->h, {f_dev})) != TPMG_OK) return st;
+    HIP_TRY(g->h, launch_dg1_factors_out(g->G, g->fac, f_dev, as_stream(stream)));
+    return TPMG_OK;
+}
+
+tpmg_status tpmg_dg1_destroy(tpmg_dg1 *g)
+{
+    delete g;
+    return TPMG_OK;
 }
 
 }  // extern "C"

@@ -172,6 +172,40 @@ hipError_t launch_axpby(size_t n, double a, const double *x, double b, const dou
 // out[v] = fixed-order sum of the G partials of value v (v < nvals <= kMultiMax)
 hipError_t launch_sum_partials(const double *partials, int G, int nvals, double *stage, double *out, hipStream_t s);
 
+// ---- next-to-lowest-order (DG1) level (dg1.hip), FP64 ------------------------
+// The DG1 level on the finest grid: six unknowns per cell, vectors in the
+// tiled storage with 6 nz rows per column (row a nz + k holds unknown a of
+// cell k), the faces of level 0, and per-k scalars.
+struct Dg1Level {
+    int n, nz, plane;
+    const double *c;    // level-0 faces [3][nz * plane] (tiled storage, nz rows)
+    const double *tab;  // [5][nz]: s_k, a_h s_k, 4 a_h s_k, 4 a_z / s_k, a_z / t_{k+1/2} (0 at the top)
+};
+enum Dg1Sweep : int {
+    DG1_SWEEP_ZERO = 0,     // out = omega H1_z^{-1} b
+    DG1_SWEEP_GENERAL = 1,  // out = u + omega H1_z^{-1} (b - H1 u)
+    DG1_SWEEP_SOLVE = 2,    // out = H1_z^{-1} b
+};
+// Band LU of every column block into fac (6 nz rows x 11 entries per column,
+// tiled by 64 columns); non-positive pivots are counted into *bad.
+hipError_t launch_dg1_factor(const Dg1Level &G, double *fac, int *bad, hipStream_t s);
+hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b,
+                            double *out, double omega, hipStream_t s);
+hipError_t launch_dg1_apply(const Dg1Level &G, const double *x, double *y, hipStream_t s);
+// r = b - H1 x (r may be null) and partial sums of (r, r)
+hipError_t launch_dg1_residual(const Dg1Level &G, const double *x, const double *b, double *r, double *partials,
+                               int *nblocks_out, hipStream_t s);
+// p_new = z + beta p_old (z when first), q = H1 p_new, partial sums of (p_new, q)
+hipError_t launch_dg1_pcg_apply(const Dg1Level &G, const double *z, const double *p_old, double *p_new, double *q,
+                                const Scalars *sc, int first, double *partials, int *nblocks_out, hipStream_t s);
+// b0 = R1 (b - H1 u) into a lowest-order level-0 vector (float when fp32)
+hipError_t launch_dg1_resid_restrict(const Dg1Level &G, const double *u, const double *b, void *b0, int fp32,
+                                     hipStream_t s);
+// u += P1 e0 (e0 a lowest-order level-0 vector, float when fp32)
+hipError_t launch_dg1_prolong(const Dg1Level &G, const void *e0, int fp32, double *u, hipStream_t s);
+// factors as [col][row][entry] with U(r, r) in entry 5
+hipError_t launch_dg1_factors_out(const Dg1Level &G, const double *fac, double *dst, hipStream_t s);
+
 // Sweep chunking for a precision, sweep mode and column height: M cells per chunk, CPW
 // chunks per wavefront, P wavefronts per 64-column tile; false if nz is not
 // supported.

@@ -38,6 +38,7 @@ STREAM_TARGET = 3     # target field x_t of the adjoint loss
 STREAM_FD_FACES = 4   # faces picked for finite-difference checks
 STREAM_TEST = 5       # test vectors
 STREAM_MIXED_RHS = 6  # right-hand side of the velocity-pressure system
+STREAM_DG1_RHS = 7    # right-hand side on the next-to-lowest-order (DG1) level
 
 _CHUNK = 1 << 22
 
@@ -158,6 +159,11 @@ class Workload:
         b[2, self.nz - 1] = 0.0
         return b
 
+    def dg1_rhs(self, seed: int = SEED) -> np.ndarray:
+        """Right-hand side on the DG1 level, (6, nz, n, n): unknown a of cell
+        (i, j, k) at logical index (a * nz + k) * n^2 + j * n + i."""
+        return normal(seed, STREAM_DG1_RHS, 6 * self.dof).reshape(6, self.nz, self.n, self.n)
+
     def target(self, seed: int = SEED) -> np.ndarray:
         return normal(seed, STREAM_TARGET, self.dof).reshape(self.nz, self.n, self.n)
 
@@ -202,6 +208,17 @@ CONFIGS = {
 }
 
 CONFIG_ORDER = list(CONFIGS)
+
+# The next-to-lowest-order (DG1, six unknowns per cell) workload.  The paper's
+# NLO grid has 5,120 columns of 64 layers (m = 384 unknowns per column); this
+# periodic grid keeps the column (64 graded layers, m = 384) and the physics of
+# the 512 x 512 x 64 workload, with 65,536 columns (25.2 M DG1 unknowns, band
+# factors of 2.2 GB) so that one GPU is filled and the data is far larger than
+# the last-level cache.  The lowest-order hierarchy below it has 5 levels
+# (coarsest 16 x 16).
+NLO_WORKLOADS = {
+    "nlo_dg1_256x256x64": Workload("nlo_dg1_256x256x64", 256, 64, 5, 1.0, 1e4, True, "uniform"),
+}
 
 
 def scaled(w: Workload, n: int, nz: int | None = None, levels: int | None = None,

@@ -1,0 +1,146 @@
+"""The next-to-lowest-order (DG1) level on the GPU against the oracle: band
+factors of the column blocks (Sec. 4.3.1), the operator, the line solve,
+the damped sweeps, the p-transfers to the lowest-order level (Sec. 4.2.1),
+the NLO V-cycle and CG, on grids that span several 64-column tiles with a
+ragged tail in k and on planes that are not a multiple of 64 (untiled
+storage)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1605_00492_amd as tp
+from gpu_util import device, host, max_rel, rel_err, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# name: n, nz, levels, a_z, graded, coarse
+CASES = {
+    "2x2x2_single_level": (2, 2, 1, 30.0, False, "direct"),
+    "4x4x3_graded": (4, 3, 2, 50.0, True, "direct"),
+    "12x12x5_untiled": (12, 5, 3, 1e3, True, "smooth"),
+    "32x32x16": (32, 16, 3, 100.0, False, "direct"),
+    "64x64x37_graded": (64, 37, 3, 1e4, True, "smooth"),
+    "96x96x24_ragged": (96, 24, 4, 1e3, True, "smooth"),
+}
+
+
+def _coeffs(n, nz, seed):
+    rng = np.random.default_rng(seed)
+    c = 1.0 + 0.5 * rng.random((3, nz, n, n))
+    c[2, nz - 1] = 0.0
+    return c
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    dev = device()
+    n, nz, levels, a_z, graded, coarse = CASES[request.param]
+    print(f"[gpu] DG1 case {request.param}", flush=True)
+    c = _coeffs(n, nz, 7 + n + nz)
+    dz = 1.05 ** np.arange(nz) if graded else None
+    kw = dict(a_h=1.0, a_z=a_z, dz=dz, levels=levels, nu=(2, 2), omega=0.8, coarse=coarse, n_coarse=2)
+    P = oracle.Problem(c, **kw)
+    G = oracle.DG1(P)
+    ct = to_dev(c)
+    H = {p: tp.Hierarchy(ct, precision=p, **kw) for p in ("fp64", "mixed")}
+    D = {p: tp.binding.DG1Level(H[p]) for p in H}
+    rng = np.random.default_rng(100 + n)
+    yield dict(name=request.param, n=n, nz=nz, P=P, G=G, H=H, D=D, rng=rng, dev=dev)
+    for d in D.values():
+        d.close()
+    for h in H.values():
+        h.close()
+
+
+def _rand(case):
+    return case["rng"].standard_normal((6, case["nz"], case["n"], case["n"]))
+
+
+def test_factors_match_oracle(case):
+    got = host(case["D"]["fp64"].factors())
+    ref = case["G"].factors()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[gpu] {case['name']} factors: {err:.2e}", flush=True)
+    assert err <= 1e-13, err
+
+
+def test_apply_matches_oracle(case):
+    x = _rand(case)
+    got = host(case["D"]["fp64"].apply(to_dev(x)))
+    err = max_rel(got, case["G"].apply(x))
+    assert err <= 1e-13, err
+
+
+def test_line_solve_matches_oracle(case):
+    r = _rand(case)
+    got = host(case["D"]["fp64"].line_solve(to_dev(r)))
+    err = rel_err(got, case["G"].line_solve(r))
+    print(f"[gpu] {case['name']} line solve: {err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("zero", [True, False])
+def test_smooth_matches_oracle(case, zero):
+    b, u = _rand(case), _rand(case)
+    D = case["D"]["fp64"]
+    got = host(D.smooth(to_dev(b), None if zero else to_dev(u)))
+    ref = case["G"].smooth(None if zero else u, b)
+    err = rel_err(got, ref)
+    assert err <= 1e-12, err
+
+
+def test_p_transfers_match_oracle(case):
+    b, u = _rand(case), _rand(case)
+    D, G = case["D"]["fp64"], case["G"]
+    got = host(D.residual_restrict(to_dev(u), to_dev(b)))
+    ref = G.restrict(b - G.apply(u))
+    assert rel_err(got, ref) <= 1e-13
+    e0 = case["rng"].standard_normal((case["nz"], case["n"], case["n"]))
+    got = host(D.prolong_add(to_dev(e0), to_dev(u)))
+    assert np.array_equal(got, G.prolong_add(e0, u))
+
+
+def test_vcycle_matches_oracle(case):
+    b = _rand(case)
+    got = host(case["D"]["fp64"].vcycle(to_dev(b)))
+    err = rel_err(got, case["G"].vcycle(b))
+    print(f"[gpu] {case['name']} V-cycle: {err:.2e}", flush=True)
+    assert err <= 1e-11, err
+
+
+def test_fp64_solve_matches_oracle_iterate(case):
+    b = _rand(case)
+    x_or, info_or = case["G"].pcg(b, rtol=1e-8, maxit=100)
+    it = info_or["iterations"]
+    x, info = case["D"]["fp64"].solve(to_dev(b), rtol=1e-8, maxit=it, flexible=False, history=True)
+    err = rel_err(host(x), x_or)
+    print(f"[gpu] {case['name']} DG1 FP64 solve: {info['iterations']} it (oracle {it}), error {err:.2e}", flush=True)
+    assert info["converged"] and info["iterations"] == it and err <= 1e-10, (info, err)
+    np.testing.assert_allclose(info["history"], info_or["history"], rtol=1e-5)
+    assert info["true_rel_residual"] <= 1.05e-8
+
+
+def test_mixed_solve_matches_oracle(case):
+    """FP32 lowest-order V-cycle inside the FP64 DG1 sweeps and CG
+    (flexible beta): the solution to 1e-8 against the oracle's FP64 one."""
+    b = _rand(case)
+    x_or, info_or = case["G"].pcg(b, rtol=1e-8, maxit=100)
+    x, info = case["D"]["mixed"].solve(to_dev(b), rtol=1e-8, maxit=100)
+    err = rel_err(host(x), x_or)
+    print(f"[gpu] {case['name']} DG1 mixed solve: {info['iterations']} it (oracle FP64 {info_or['iterations']}), "
+          f"true rel residual {info['true_rel_residual']:.2e}, error vs oracle {err:.2e}", flush=True)
+    assert info["converged"] and info["true_rel_residual"] <= 1.05e-8
+    assert err <= 1e-8, err
+
+
+def test_dg1_argument_errors(case):
+    D = case["D"]["fp64"]
+    if case["name"] != "32x32x16":
+        pytest.skip("one case suffices")
+    L = tp.lib()
+    import ctypes as C
+    x = torch.zeros(D.shape, dtype=torch.float64, device=case["dev"])
+    assert L.tpmg_dg1_apply(None, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), None) == -1
+    assert L.tpmg_dg1_apply(D.handle, None, C.c_void_p(x.data_ptr()), None) == -1
+    assert L.tpmg_dg1_vcycle(D.handle, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), None) == -1
