@@ -160,11 +160,12 @@ def cpu_protocol(args):
 
 
 def probe(tp, torch, w, c, b, kw, args):
-    """Each finest-level kernel of the V-cycle (both precisions) and a plain
-    1 GiB device copy, timed with HIP events: the workload for rocprofv3
-    counter passes and for kernel tuning.  Algorithmic bytes per DOF are
-    words x word size: sweep0 5, sweep 6, prolongation+sweep 6.25,
-    residual+restriction 5.25, apply 5."""
+    """Each finest-level kernel of the V-cycle (both precisions), the face
+    gradient and a plain 1 GiB device copy, timed with HIP events: the
+    workload for rocprofv3 counter passes and for kernel tuning.  Algorithmic
+    bytes per DOF are words x word size: sweep0 5, sweep 6,
+    prolongation+sweep 6.25, residual+restriction 5.25, apply 5, face
+    gradient 5 (FP64)."""
     H = tp.Hierarchy(c, precision="mixed", **kw)
     nc = H.level_n(1)
     res = {}
@@ -180,6 +181,11 @@ def probe(tp, torch, w, c, b, kw, args):
             "restrict": (lambda: H.residual_restrict(u, bb), 5.25),
             "apply": (lambda: H.apply(u), 5.0),
         }
+        if S == 8:
+            # adjoint face gradient: lambda, x in; three face arrays out
+            lam = torch.empty_like(bb).normal_()
+            g = torch.empty((3,) + tuple(bb.shape), dtype=dt, device=c.device)
+            kernels["face_gradient"] = (lambda: H.face_gradient(lam, u, out=g), 5.0)
         for name, (fn, words) in kernels.items():
             fn()
             torch.cuda.synchronize()

@@ -54,22 +54,30 @@ __device__ __forceinline__ Rsrc make_rsrc(const void *p, size_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, kRsrcWord3);
 }
 
+// AUX: the cache policy of the access; kNT (2) marks it non-temporal, a
+// stream the L2 should give up first (data read or written once), so that
+// lines other workgroups will read again stay resident.
+constexpr int kNT = 2;
+template <int AUX = 0>
 __device__ __forceinline__ float bload(float, Rsrc r, unsigned voff, unsigned soff)
 {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ double bload(double, Rsrc r, unsigned voff, unsigned soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bstore(float v, Rsrc r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bstore(double v, Rsrc r, unsigned voff, unsigned soff)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                          (int)voff, (int)soff, 0);
+                                          (int)voff, (int)soff, AUX);
 }
 
 struct Nbr {

@@ -223,8 +223,25 @@ __device__ __forceinline__ unsigned row_lane_off(unsigned ic, int nz, unsigned S
 // with per-lane offsets for all five neighbours; held to 64 (eight
 // wavefronts per SIMD, two 1024-thread workgroups per CU) it runs 0.86
 // instead of 1.11 ms at 1024^2 x 128.
-template <typename T, int M, int CPW, int MODE, int LB, bool ROWS>
-__global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1) ? 8 : 1) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
+// CP: cache policy of the data read or written once per cell (b, c_U, the
+// output): kNT leaves L2 to the data other workgroups read again (u and c_N
+// by the north / south rows, c_E by the east column).
+//
+// Launch bounds: the FP32 prolongation sweep (8-cell chunks) is held to 64
+// VGPRs and the FP64 sweep from zero (16-cell chunks) to 128, so that two
+// workgroups share a CU (measured at 1024^2 x 128: FP64 sweep from zero 1.06
+// vs 1.21 ms with 28 bytes/lane of spill; the FP64 general sweep, held the
+// same way, spills 188 bytes/lane and ran slower).
+template <typename T, int M, int CPW, int MODE, int LB>
+constexpr int sweep_min_waves()
+{
+    if (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1) return 8;
+    if (MODE == SWEEP_ZERO && LB == 512 && sizeof(T) == 8 && M == 16 && CPW == 1) return 4;
+    return 1;
+}
+
+template <typename T, int M, int CPW, int MODE, int LB, bool ROWS, int CP>
+__global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ ec, T omega,
                                               int tbi, int tbj)
 {
@@ -306,11 +323,15 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
     const Rsrc ru = MODE == SWEEP_ZERO ? make_rsrc(u, 0) : rs(u, fbase, fbytes);
     const Rsrc re = MODE == SWEEP_PROLONG ? rs(ec, cbase, (size_t)nz * planec * S) : make_rsrc(ec, 0);
     auto ld = [&](const Rsrc &r, Off o, int k) -> T { return bload(T(), r, o.v, o.s + (unsigned)k * pstride); };
+    auto ld1 = [&](const Rsrc &r, Off o, int k) -> T {
+        return bload<CP>(T(), r, o.v, o.s + (unsigned)k * pstride);
+    };
     auto U = [&](int k, Off o, Off po) -> T {
         T v = ld(ru, o, k);
         if (MODE == SWEEP_PROLONG) v += bload(T(), re, po.v, po.s + (unsigned)k * cstride);
         return v;
     };
+
 
     ChunkState<T, M> cs[CPW];
     T su[CPW][M];
@@ -338,12 +359,12 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
         for (int c = 0; c < CPW; ++c) {
             const int k = k0[c] + t;
             if (k < nz) {
-                R[c].b = ld(rb, C, k);
+                R[c].b = ld1(rb, C, k);
                 R[c].cE = ld(rE, C, k);
                 R[c].cEw = ld(rE, W, k);
                 R[c].cN = ld(rN, C, k);
                 R[c].cNs = ld(rN, Sx, k);
-                R[c].cU = ld(rU, C, k);
+                R[c].cU = ld1(rU, C, k);
                 R[c].uup = R[c].uE = R[c].uW = R[c].uN = R[c].uS = T(0);
                 if (MODE != SWEEP_ZERO) {
                     if (k + 1 < nz) R[c].uup = U(k + 1, C, PC);
@@ -401,7 +422,8 @@ __global__ __launch_bounds__(LB, (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int k = k0[c] + t;
-            if (k < nz) bstore(su[c][t] + omega * cs[c].value(t, xlo, xhi), ro, oo, C.s + (unsigned)k * pstride);
+            if (k < nz)
+                bstore<CP>(su[c][t] + omega * cs[c].value(t, xlo, xhi), ro, oo, C.s + (unsigned)k * pstride);
         }
     }
 }
@@ -545,7 +567,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
 // cell (every load a contiguous segment), adds the horizontal child pair by
 // a lane exchange, and wavefront 0 adds row 2J+1's pair sums from LDS and
 // writes the 32 coarse values of the tile per level.
-template <typename T, int KC>
+template <typename T, int KC, int CP>
 __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T *__restrict__ u,
                                                              const T *__restrict__ b, T *__restrict__ bc)
 {
@@ -579,13 +601,13 @@ __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T
             const unsigned sk = (unsigned)k * R.pstride;
             const T up = (k + 1 < nz) ? bload(T(), ru, R.oc, sk + R.pstride) : T(0);
             const T h = L.wh[k];
-            const T wU = L.wz[k] * bload(T(), R.rU, R.oc, sk);
+            const T wU = L.wz[k] * bload<CP>(T(), R.rU, R.oc, sk);
             const T hu = L.mu[k] * uc + h * bload(T(), R.rE, R.oc, sk) * (uc - bload(T(), ru, R.oe, sk)) +
                          h * bload(T(), R.rE, R.ow, sk) * (uc - bload(T(), ru, R.ow, sk)) +
                          h * bload(T(), R.rN, R.oc, sk) * (uc - bload(T(), ru, R.on, sk)) +
                          h * bload(T(), R.rN, R.os, sk) * (uc - bload(T(), ru, R.os, sk)) + wU * (uc - up) +
                          wD * (uc - um);
-            const T r = bload(T(), rb, R.oc, sk) - hu;
+            const T r = bload<CP>(T(), rb, R.oc, sk) - hu;
             rs[q] = r + __shfl_xor(r, 1, 64);  // children (2I, j) + (2I+1, j)
             um = uc;
             uc = up;
@@ -605,7 +627,7 @@ __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
             const int k = k0 + q;
-            if (k < nz) bstore(rs[q] + pair[q][lane >> 1], rc, oo, (unsigned)k * cstride);
+            if (k < nz) bstore<CP>(rs[q] + pair[q][lane >> 1], rc, oo, (unsigned)k * cstride);
         }
     }
 }
@@ -1125,6 +1147,15 @@ __global__ __launch_bounds__(256) void k_probe_copy(const v4u *__restrict__ s, v
 
 
 
+// Levels of at least 2^24 cells (an FP32 vector of 64 MiB; the six arrays a
+// sweep streams exceed the 256 MB last-level cache) use non-temporal hints
+// for the data they read or write once.
+template <typename T>
+bool nt_level(const Level<T> &L)
+{
+    return (size_t)L.plane * L.nz >= ((size_t)1 << 24);
+}
+
 // k-chunk of a streaming kernel: `dflt` unless TPMG_KCHUNK overrides it.
 // Measured on 1024^2 x 128: longer chunks help the FP64 CG stencils (64
 // cells: 1.68 vs 1.77 ms) and the finest restriction (32: 0.685 vs 0.70 ms);
@@ -1177,9 +1208,20 @@ hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, 
     static const int erows = env_int("TPMG_SWEEP_ROWS");
     const bool fits = L.n % 64 == 0 && (mode != SWEEP_PROLONG || L.n % 128 == 0);
     const bool rows = fits && (erows == 1 || (erows < 0 && sizeof(T) == 4 && mode == SWEEP_PROLONG));
+    // Non-temporal accesses for b, c_U and the output on levels too large
+    // for the caches (TPMG_SWEEP_NT=0: plain everywhere, 1: everywhere):
+    // measured at 1024^2 x 128, FP32 V-cycle 4.36 vs 4.51 ms; on levels whose
+    // data stays in the last-level cache the next kernel's reads of b are
+    // hits that the hints would give away.
+    static const int ent = env_int("TPMG_SWEEP_NT");
+    const bool nt = ent == 1 || (ent != 0 && nt_level(L));
     auto go = [&](auto mc, auto rc) {
-        hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value>), dim3(tiles), block, lds,
-                           s, L, u, b, out, ec, omega, tbi, tbj);
+        if (nt)
+            hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value, kNT>), dim3(tiles),
+                               block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
+        else
+            hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value, 0>), dim3(tiles),
+                               block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
     };
     using RT = std::true_type;
     using RF = std::false_type;
@@ -1274,7 +1316,12 @@ hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *b
     if ((L.n & 63) == 0 && sizeof(T) == 4) {
         const int kc = 16, nkc = (L.nz + kc - 1) / kc;
         const int grid = nkc * (L.n / 2) * (L.n / 64);
-        hipLaunchKernelGGL((k_resid_restrict_rows<T, 16>), dim3(grid), dim3(128), 0, s, L, u, b, bc);
+        // non-temporal b, c_U and output, as in the sweep (TPMG_RESTRICT_NT=0: plain)
+        static const int ent = env_int("TPMG_RESTRICT_NT");
+        if (ent == 1 || (ent != 0 && nt_level(L)))
+            hipLaunchKernelGGL((k_resid_restrict_rows<T, 16, kNT>), dim3(grid), dim3(128), 0, s, L, u, b, bc);
+        else
+            hipLaunchKernelGGL((k_resid_restrict_rows<T, 16, 0>), dim3(grid), dim3(128), 0, s, L, u, b, bc);
         return hipGetLastError();
     }
     const int planec = (L.n / 2) * (L.n / 2);
@@ -1488,8 +1535,8 @@ hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const
 {
     // Measured at 1024^2 x 128: non-temporal stores and 64-cell chunks 1.218 ms,
     // plain stores 1.266 ms (64) / 1.328 ms (16 cells); TPMG_FG_NT=0 restores
-    // plain stores.
-    const int kc = stream_kc(64);
+    // plain stores.  Planes below 512^2 keep 16-cell chunks (more workgroups).
+    const int kc = stream_kc(L.plane >= (1 << 18) ? 64 : 16);
     static const int nt = env_int("TPMG_FG_NT");
     return with_kc(kc, [&](auto KCc) {
         if (nt != 0)

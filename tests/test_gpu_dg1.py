@@ -144,3 +144,50 @@ def test_dg1_argument_errors(case):
     assert L.tpmg_dg1_apply(None, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), None) == -1
     assert L.tpmg_dg1_apply(D.handle, None, C.c_void_p(x.data_ptr()), None) == -1
     assert L.tpmg_dg1_vcycle(D.handle, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), None) == -1
+
+
+def test_nlo_workload_matches_oracle():
+    """The benchmark's NLO workload in full (256 x 256 x 64 graded, 25.2 M DG1
+    unknowns, five lowest-order levels): band factors of sampled columns, one
+    NLO V-cycle, the FP64 CG at the oracle's iteration count and the mixed CG
+    against the oracle's FP64 solution."""
+    import synthetic as syn
+    dev = device()
+    w = syn.NLO_WORKLOADS["nlo_dg1_256x256x64"]
+    print(f"[gpu] DG1 at full size: {w.name}", flush=True)
+    c, b = w.coefficients(), w.dg1_rhs()
+    kw = dict(dz=w.dz(), a_h=w.a_h, a_z=w.a_z, levels=w.levels, nu=w.nu, omega=w.omega, coarse=w.coarse,
+              n_coarse=w.n_coarse)
+    P = oracle.problem_for(w, c)
+    G = oracle.DG1(P)
+    ct, bt = to_dev(c), to_dev(b)
+    H = tp.Hierarchy(ct, precision="fp64", **kw)
+    D = tp.DG1Level(H)
+    F = D.factors()
+    rng = np.random.default_rng(11)
+    cols = [(0, 0), (255, 255), (0, 255), (255, 0)] + [tuple(v) for v in rng.integers(0, 256, size=(28, 2))]
+    Fo = G.factors()
+    for (j, i) in cols:
+        got = F[j, i].cpu().numpy()
+        ref = Fo[j, i]
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (j, i)
+    del Fo, F
+    e = rel_err(host(D.vcycle(bt)), G.vcycle(b))
+    print(f"[gpu] {w.name} NLO V-cycle: {e:.2e}", flush=True)
+    assert e <= 1e-11, e
+    x_or, info_or = G.pcg(b, rtol=w.rtol, maxit=100)
+    x, info = D.solve(bt, rtol=w.rtol, maxit=info_or["iterations"], flexible=False)
+    err = rel_err(host(x), x_or)
+    print(f"[gpu] {w.name} FP64 CG: {info['iterations']} it (oracle {info_or['iterations']}), error {err:.2e}",
+          flush=True)
+    assert info["converged"] and info["iterations"] == info_or["iterations"] and err <= 1e-10, (info, err)
+    D.close()
+    H.close()
+    Hm = tp.Hierarchy(ct, precision="mixed", **kw)
+    Dm = tp.DG1Level(Hm)
+    x, info = Dm.solve(bt, rtol=w.rtol, maxit=100)
+    err = rel_err(host(x), x_or)
+    print(f"[gpu] {w.name} mixed CG: {info['iterations']} it, error vs oracle {err:.2e}", flush=True)
+    assert info["converged"] and err <= 1e-8, (info, err)
+    Dm.close()
+    Hm.close()

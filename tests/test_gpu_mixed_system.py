@@ -30,6 +30,7 @@ CASES = {
     "graded64x32_cfl8": (64, 32, 3, 16.0, 1e4, True, "smooth"),
     "single_level32x16": (32, 16, 1, 16.0, 1e4, True, "smooth"),
     "tiny2x3": (2, 3, 1, 1.0, 10.0, False, "smooth"),
+    "graded256x32_cfl8": (256, 32, 5, 16.0, 1e4, True, "smooth"),
 }
 
 
