@@ -36,29 +36,32 @@ SWEEP_WORDS = 6            # reads u, b, c_E, c_N, c_U; writes u'
 VCYCLE_WORDS = 28.5 * 4 / 3  # 28.5 words on the finest level, times sum 4^-l
 KERNEL_SOURCES = ["paper_1605_00492_amd/csrc/tpmg_kernels.hip", "paper_1605_00492_amd/csrc/tpmg_device.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_1024x1024x128_counters.json")
+DG1_SOURCES = ["paper_1605_00492_amd/csrc/tpmg_dg1.hip", "paper_1605_00492_amd/csrc/tpmg_device.h"]
+DG1_COUNTERS_FILE = os.path.join(ROOT, "profiles", "dg1_sweep_256x256x64_counters.json")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch_dof: int):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def measured_traffic(launch_dof: int, path=COUNTERS_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of the roofline kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_hash() or d.get("dof") != launch_dof:
+    if d.get("kernel_source_hash") != kernel_hash(sources) or d.get("dof") != launch_dof:
         return None
     return d.get("bytes_per_launch")
 
@@ -402,7 +405,9 @@ def nlo(tp, torch, dev, args):
         H.close()
     out["roofline"] = {"kernel": "k_dg1_sweep (general): residual + band forward/back substitution + update",
                        "bound": "hbm", "achieved": out["runs"][0]["sweep_GBps"], "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": out["runs"][0]["sweep_frac_hbm_peak"], "traffic": None,
+                       "unit": "GB/s", "frac": out["runs"][0]["sweep_frac_hbm_peak"],
+                       "traffic": measured_traffic(nv, DG1_COUNTERS_FILE, DG1_SOURCES),
+                       "kernel_source_hash": kernel_hash(DG1_SOURCES),
                        "algorithmic_bytes_per_launch": 116 * nv, "launch_ms": out["runs"][0]["sweep_ms"]}
     if not args.no_cpu_baseline:
         oracle = native_oracle()

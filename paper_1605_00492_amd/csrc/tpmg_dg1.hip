@@ -345,7 +345,10 @@ struct Dg1Bwd {
 // (the stores go through the same kind of buffer access, so the compiler
 // keeps loads that follow a store in program order behind it); with PF the
 // forward loads of cell k + 1 are issued before the stores of cell k.
-template <int MODE, bool PF>
+// CP: cache policy of the data the sweep reads or writes once (the band
+// factors, b, the final output); y, written in the forward pass and read back
+// in the backward pass, and u keep the default policy.
+template <int MODE, bool PF, int CP>
 __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__restrict__ fac,
                                                    const double *__restrict__ u, const double *__restrict__ b,
                                                    double *__restrict__ out, double omega)
@@ -356,12 +359,13 @@ __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__r
     const Rsrc ru = make_rsrc(u ? u : b, vbytes), rb = make_rsrc(b, vbytes), ro = make_rsrc(out, vbytes);
     const unsigned oo = q.active ? q.ov : 0xFFFFFFFFu;
     auto load_fwd = [&](Dg1Fwd &F, unsigned k) {
-        ld6(F.b, rb, q.ov, k, nz, q.row);
+#pragma unroll
+        for (int a = 0; a < kNb; ++a) F.b[a] = bload<CP>(double(), rb, q.ov, (a * nz + k) * q.row);
 #pragma unroll
         for (int a = 0; a < kNb; ++a)
 #pragma unroll
             for (int e = 0; e < 5; ++e)
-                F.l[a][e] = bload(double(), q.rF, q.of, ((kNb * k + a) * kNf + e) * q.row);
+                F.l[a][e] = bload<CP>(double(), q.rF, q.of, ((kNb * k + a) * kNf + e) * q.row);
     };
     auto load_bwd = [&](Dg1Bwd &B, unsigned k) {
         ld6(B.y, ro, q.ov, k, nz, q.row);
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__r
         for (int a = 0; a < kNb; ++a)
 #pragma unroll
             for (int e = 0; e < 6; ++e)
-                B.u[a][e] = bload(double(), q.rF, q.of, ((kNb * k + a) * kNf + 5 + e) * q.row);
+                B.u[a][e] = bload<CP>(double(), q.rF, q.of, ((kNb * k + a) * kNf + 5 + e) * q.row);
     };
 
     double yw[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // y(r-1) .. y(r-5)
@@ -451,7 +455,7 @@ __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__r
             else o[a] = x;
         }
 #pragma unroll
-        for (int a = 0; a < kNb; ++a) bstore(o[a], ro, oo, ((unsigned)a * nz + (unsigned)k) * q.row);
+        for (int a = 0; a < kNb; ++a) bstore<CP>(o[a], ro, oo, ((unsigned)a * nz + (unsigned)k) * q.row);
         if (k > 0) {
             if constexpr (PF) B = Bn;
             else load_bwd(B, (unsigned)k - 1);
@@ -689,17 +693,17 @@ hipError_t launch_dg1_factor(const Dg1Level &G, double *fac, int *bad, hipStream
     return hipGetLastError();
 }
 
-template <bool PF>
+template <bool PF, int CP>
 void dg1_sweep_pf(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b, double *out,
                   double omega, hipStream_t s)
 {
     const dim3 grid(dg1_blocks(G.plane)), block(256);
     if (mode == DG1_SWEEP_GENERAL)
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_GENERAL, PF>), grid, block, 0, s, G, fac, u, b, out, omega);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_GENERAL, PF, CP>), grid, block, 0, s, G, fac, u, b, out, omega);
     else if (mode == DG1_SWEEP_ZERO)
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_ZERO, PF>), grid, block, 0, s, G, fac, nullptr, b, out, omega);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_ZERO, PF, CP>), grid, block, 0, s, G, fac, nullptr, b, out, omega);
     else
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_SOLVE, PF>), grid, block, 0, s, G, fac, nullptr, b, out, 1.0);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_SOLVE, PF, CP>), grid, block, 0, s, G, fac, nullptr, b, out, 1.0);
 }
 
 hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b,
@@ -709,10 +713,17 @@ hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, cons
     // of this cell's stores (256 VGPRs in the general form); measured at
     // 256^2 x 64 it ran as fast as the default (0.717 vs 0.713 ms)
     static const int pf = env_int("TPMG_DG1_PF");
+    // Non-temporal factors, b and output when the factors exceed the 256 MB
+    // last-level cache (TPMG_DG1_NT=0: never, 1: always): measured at
+    // 256^2 x 64 (2.2 GB of factors), general sweep 0.646 vs 0.715 ms.
+    static const int nt = env_int("TPMG_DG1_NT");
+    const bool big = (size_t)G.plane * kNb * G.nz * kNf * 8 >= ((size_t)1 << 28);
     if (pf == 1)
-        dg1_sweep_pf<true>(G, fac, mode, u, b, out, omega, s);
+        dg1_sweep_pf<true, 0>(G, fac, mode, u, b, out, omega, s);
+    else if (nt == 1 || (nt != 0 && big))
+        dg1_sweep_pf<false, kNT>(G, fac, mode, u, b, out, omega, s);
     else
-        dg1_sweep_pf<false>(G, fac, mode, u, b, out, omega, s);
+        dg1_sweep_pf<false, 0>(G, fac, mode, u, b, out, omega, s);
     return hipGetLastError();
 }
 

@@ -840,7 +840,8 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // forms level k, and holds z in its stored type until it is used: two
 // levels in flight at 80 VGPRs (6 wavefronts per SIMD) instead of one at
 // 54 (8 per SIMD); 1.45 vs 1.74 ms at 1024^2 x 128 with FP32 z.
-template <int KC, typename ZT>
+// CP: cache policy of c_U and of the p, q stores (read or written once).
+template <int KC, typename ZT, int CP>
 __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const ZT *__restrict__ zt,
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
@@ -886,7 +887,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
         w.cEw = bload(double(), R.rE, R.ow, sk);
         w.cN = bload(double(), R.rN, R.oc, sk);
         w.cNs = bload(double(), R.rN, R.os, sk);
-        w.cU = bload(double(), R.rU, R.oc, sk);
+        w.cU = bload<CP>(double(), R.rU, R.oc, sk);
         w.zu = ZT(0);
         w.pu = 0.0;
         if (k + 1 < nz) {
@@ -918,8 +919,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             const double qq = L.mu[k] * pc + h * cur.cE * (pc - comb(cur.zE, cur.pE)) +
                               h * cur.cEw * (pc - comb(cur.zW, cur.pW)) + h * cur.cN * (pc - comb(cur.zN, cur.pN)) +
                               h * cur.cNs * (pc - comb(cur.zS, cur.pS)) + wU * (pc - pp) + wD * (pc - pm);
-            bstore(pc, rpn, oo, sk);
-            bstore(qq, rq, oo, sk);
+            bstore<CP>(pc, rpn, oo, sk);
+            bstore<CP>(qq, rq, oo, sk);
             if (active) acc_pq += pc * qq;
             pm = pc;
             pc = pp;
@@ -1464,14 +1465,23 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     const int kc = stream_kc(16);
     const int G = stream_grid(L, kc);
     *nblocks_out = G;
+    // Non-temporal c_U and p, q stores on levels larger than the caches
+    // (TPMG_CG_NT=0: never, 1: always): 1.39 vs 1.45 ms at 1024^2 x 128.
+    static const int ent = env_int("TPMG_CG_NT");
+    const bool nt = ent == 1 || (ent != 0 && nt_level(L));
     return with_kc(kc, [&](auto KCc) {
         constexpr int K = decltype(KCc)::value;
-        if (z32)
-            hipLaunchKernelGGL((k_pcg_apply<K, float>), dim3(G), dim3(kStreamThreads), 0, s, L, z32, p_old, p_new, q,
-                               sc, first, partials);
-        else
-            hipLaunchKernelGGL((k_pcg_apply<K, double>), dim3(G), dim3(kStreamThreads), 0, s, L, z, p_old, p_new, q,
-                               sc, first, partials);
+        auto go = [&](auto cp) {
+            constexpr int CP = decltype(cp)::value;
+            if (z32)
+                hipLaunchKernelGGL((k_pcg_apply<K, float, CP>), dim3(G), dim3(kStreamThreads), 0, s, L, z32, p_old,
+                                   p_new, q, sc, first, partials);
+            else
+                hipLaunchKernelGGL((k_pcg_apply<K, double, CP>), dim3(G), dim3(kStreamThreads), 0, s, L, z, p_old,
+                                   p_new, q, sc, first, partials);
+        };
+        if (nt) go(std::integral_constant<int, kNT>());
+        else go(std::integral_constant<int, 0>());
         return hipGetLastError();
     });
 }

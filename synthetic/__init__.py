@@ -218,6 +218,8 @@ CONFIG_ORDER = list(CONFIGS)
 # (coarsest 16 x 16).
 NLO_WORKLOADS = {
     "nlo_dg1_256x256x64": Workload("nlo_dg1_256x256x64", 256, 64, 5, 1.0, 1e4, True, "uniform"),
+    # four times the columns (100.7 M DG1 unknowns, band factors of 8.9 GB)
+    "nlo_dg1_512x512x64": Workload("nlo_dg1_512x512x64", 512, 64, 6, 1.0, 1e4, True, "uniform"),
 }
 
 

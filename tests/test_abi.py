@@ -100,6 +100,22 @@ def test_null_arguments_rejected_on_host(tp):
     assert L.tpmg_level_n(None, 0) == -1
     assert L.tpmg_bandwidth_probe(None, None, 16, None) == -1
     assert b"NULL" in L.tpmg_last_error(None) or L.tpmg_last_error(None)
+    # the static-scratch apply and the DG1 entry points: NULL handles
+    assert L.tpmg_apply_operator_static(None, 0, 0, None, None, 0, None) == -1
+    nb = C.c_size_t(0)
+    assert L.tpmg_dg1_workspace_bytes(None, C.byref(nb)) == -1
+    g = C.c_void_p()
+    assert L.tpmg_dg1_setup(None, None, 0, None, C.byref(g)) == -1
+    for name in ("tpmg_dg1_apply", "tpmg_dg1_line_solve", "tpmg_dg1_vcycle", "tpmg_dg1_prolong_add"):
+        assert getattr(L, name)(None, None, None, None) == -1, name
+    assert L.tpmg_dg1_smooth(None, None, None, None, None) == -1
+    assert L.tpmg_dg1_residual_restrict(None, None, None, None, None) == -1
+    assert L.tpmg_dg1_solve(None, None, None, None, None, None) == -1
+    assert L.tpmg_dg1_factors(None, None, None) == -1
+    assert L.tpmg_dg1_destroy(None) == 0
+    assert L.tpmg_profile_enable(None, 1) == -1
+    ms, cnt = C.c_double(0), C.c_int64(0)
+    assert L.tpmg_profile_read_level(None, 0, C.byref(ms), C.byref(cnt)) == -1
 
 
 def test_status_strings(tp):
