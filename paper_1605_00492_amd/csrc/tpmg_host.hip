@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -213,6 +214,8 @@ Level<T> level_view(const tpmg_hierarchy *h, int l)
     L.mu = (const T *)B.mu;
     L.wh = (const T *)B.wh;
     L.wz = (const T *)B.wz;
+    static const char *ef = getenv("TPMG_FULL_CHUNKS");
+    L.full_chunks = !(ef && atoi(ef) == 0);
     return L;
 }
 

@@ -41,6 +41,10 @@ struct Level {
     const T *mu;    // [nz]  mass 4^l s_k
     const T *wh;    // [nz]  horizontal factor a_h s_k
     const T *wz;    // [nz]  vertical factor 4^l a_z / t_{k+1/2}; wz[nz-1] = 0
+    // Kernels that walk a chunk of a column take an unguarded path when the
+    // chunk lies inside it; 0 forces the guarded path everywhere (for
+    // comparison; TPMG_FULL_CHUNKS=0).
+    int full_chunks = 1;
 };
 
 // Forms of the line-relaxation sweep kernel.

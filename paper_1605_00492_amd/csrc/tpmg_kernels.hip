@@ -181,8 +181,34 @@ __device__ __forceinline__ void coupling_solve(T *red, int Q, int lane)
 
 template <typename T>
 struct SweepRaw {
-    T uup, uE, uW, uN, uS, b, cE, cEw, cN, cNs, cU;
+    T uup, uE, uW, uN, uS, b, cE, cEw, cN, cNs, cU, eup;
 };
+
+// Wavefront shifts by one lane (DPP): lane i receives v from lane i - 1
+// (lane_from_prev) or i + 1 (lane_from_next); the lane without a source
+// (0, resp. 63) keeps `edge`.  All 64 lanes must be active.
+__device__ __forceinline__ int dpp_shr1(int edge, int v) { return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_shl1(int edge, int v) { return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ float lane_from_prev(float edge, float v)
+{
+    return __int_as_float(dpp_shr1(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ float lane_from_next(float edge, float v)
+{
+    return __int_as_float(dpp_shl1(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_from_prev(double edge, double v)
+{
+    const long long e = __double_as_longlong(edge), x = __double_as_longlong(v);
+    const int lo = dpp_shr1((int)e, (int)x), hi = dpp_shr1((int)(e >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_next(double edge, double v)
+{
+    const long long e = __double_as_longlong(edge), x = __double_as_longlong(v);
+    const int lo = dpp_shl1((int)e, (int)x), hi = dpp_shl1((int)(e >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // Tile order of the sweep: tiles (64 columns of one row) are grouped into
 // blocks of bi tiles x bj rows numbered consecutively, so that the workgroups
@@ -210,19 +236,24 @@ __device__ __forceinline__ unsigned row_lane_off(unsigned ic, int nz, unsigned S
     return ((ic >> 6) * (unsigned)nz * 64u + (ic & 63u)) * S;
 }
 
-// ROWS: the rows are whole tiles (n % 64 == 0; for the prolongation sweep
-// also n / 2 % 64 == 0).  A wavefront then covers 64 columns of one row, so
-// its north / south (and parent) rows are wave-uniform offsets: the buffers
-// are addressed from the lowest of the rows involved, with the row part of
-// every offset in a scalar register and only the centre, east and west
-// columns (and their parents) per lane.  At its 64-VGPR bound the FP32
-// prolongation sweep then spills 8 instead of 16 bytes per lane (0.80 vs
-// 0.86 ms at 1024^2 x 128).
+// RM (row mode) 1 and 2: the rows are whole tiles (n % 64 == 0; for the
+// prolongation sweep also n / 2 % 64 == 0).  A wavefront then covers 64
+// columns of one row, so its north / south (and parent) rows are
+// wave-uniform offsets: the buffers are addressed from the lowest of the rows
+// involved, with the row part of every offset in a scalar register and only
+// the centre, east and west columns (and their parents) per lane.  At its
+// 64-VGPR bound the FP32 prolongation sweep then spills 8 instead of 16
+// bytes per lane (0.80 vs 0.86 ms at 1024^2 x 128).  RM 2 also takes the
+// east / west values of u from the neighbouring lanes (one load at the tile
+// edges instead of two per cell) and, in the prolongation sweep, reads one
+// parent row less: 13 instead of 16 loads per cell and no spill.
 //
 // The FP32 prolongation sweep with 8-cell chunks needs more than 64 VGPRs
 // with per-lane offsets for all five neighbours; held to 64 (eight
-// wavefronts per SIMD, two 1024-thread workgroups per CU) it runs 0.86
-// instead of 1.11 ms at 1024^2 x 128.
+// wavefronts per SIMD, two 1024-thread workgroups per CU) it ran 0.86
+// instead of 1.11 ms at 1024^2 x 128.  With per-lane offsets (RM 0: levels
+// whose rows are not whole tiles, all small) it is not held, since the spill
+// costs more than occupancy gains on a level that fills few CUs.
 // CP: cache policy of the data read or written once per cell (b, c_U, the
 // output): kNT leaves L2 to the data other workgroups read again (u and c_N
 // by the north / south rows, c_E by the east column).
@@ -232,20 +263,26 @@ __device__ __forceinline__ unsigned row_lane_off(unsigned ic, int nz, unsigned S
 // workgroups share a CU (measured at 1024^2 x 128: FP64 sweep from zero 1.06
 // vs 1.21 ms with 28 bytes/lane of spill; the FP64 general sweep, held the
 // same way, spills 188 bytes/lane and ran slower).
-template <typename T, int M, int CPW, int MODE, int LB>
+template <typename T, int M, int CPW, int MODE, int LB, int RM, bool FULL>
 constexpr int sweep_min_waves()
 {
-    if (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1) return 8;
+    if (MODE == SWEEP_PROLONG && LB == 1024 && sizeof(T) == 4 && M == 8 && CPW == 1 && RM != 0 && !FULL) return 8;
     if (MODE == SWEEP_ZERO && LB == 512 && sizeof(T) == 8 && M == 16 && CPW == 1) return 4;
     return 1;
 }
 
-template <typename T, int M, int CPW, int MODE, int LB, bool ROWS, int CP>
-__global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
+template <typename T, int M, int CPW, int MODE, int LB, int RM, int CP, bool FULL>
+__global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB, RM, FULL>())) void k_sweep(Level<T> L, const T *__restrict__ u, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ ec, T omega,
                                               int tbi, int tbj)
 {
     constexpr unsigned S = sizeof(T);
+    constexpr bool ROWS = RM != 0;
+    // XL: east / west values of u from the neighbouring lanes; XP: in the
+    // prolongation sweep, the parent correction of the cell carried along k
+    // and reused for whichever of its north / south neighbours shares it.
+    constexpr bool XL = RM == 2 && MODE != SWEEP_ZERO;
+    constexpr bool XP = XL && MODE == SWEEP_PROLONG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *red = reinterpret_cast<T *>(smem_raw);  // [Q][8][64]
 
@@ -265,8 +302,12 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
 
     // Fine offsets C (centre), E, W, N, Sx and parent offsets PC .. PS;
     // fine buffers start at byte fbase, the coarse one at cbase.
-    Off C, E, W, N, Sx, PC{0, 0}, PE{0, 0}, PW{0, 0}, PN{0, 0}, PS{0, 0};
+    // X (with XL): the neighbour across the tile edge, west for lane 0 and
+    // east for lane 63 (the other lanes read their own cell); PX its parent;
+    // PO the parent row that differs from the cell's own.
+    Off C, E, W, N, Sx, X{0, 0}, PC{0, 0}, PE{0, 0}, PW{0, 0}, PN{0, 0}, PS{0, 0}, PX{0, 0}, PO{0, 0};
     size_t fbase = 0, cbase = 0;
+    bool jodd = false;
     if constexpr (ROWS) {
         const int TR = L.n >> 6, j = tile / TR, ti = tile - j * TR;
         const int jn = (j + 1 == L.n) ? 0 : j + 1, js = (j == 0) ? L.n - 1 : j - 1;
@@ -282,6 +323,8 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
         W = {ow, sc};
         N = {ov, (unsigned)(jn - j0) * rowb};
         Sx = {ov, (unsigned)(js - j0) * rowb};
+        X = {lane == 0 ? ow : (lane == 63 ? oe : ov), sc};
+        jodd = j & 1;
         if (MODE == SWEEP_PROLONG) {
             const int jc = j >> 1, jcn = jn >> 1, jcs = js >> 1, jc0 = min(jc, min(jcn, jcs));
             const unsigned rowc = (unsigned)(nc >> 6) * nz * 64u * S;
@@ -294,6 +337,10 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
             PW = {row_lane_off(iw >> 1, nz, S), scc};
             PN = {pv, (unsigned)(jcn - jc0) * rowc};
             PS = {pv, (unsigned)(jcs - jc0) * rowc};
+            PX = lane == 0 ? PW : (lane == 63 ? PE : PC);
+            // j even: the north neighbour has the cell's parent row, j odd
+            // the south one (rows 2 jc and 2 jc + 1 share parent row jc)
+            PO = jodd ? PN : PS;
         }
     } else {
         const Nbr nb = neighbours(cc, L.n, plane);
@@ -326,31 +373,47 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
     auto ld1 = [&](const Rsrc &r, Off o, int k) -> T {
         return bload<CP>(T(), r, o.v, o.s + (unsigned)k * pstride);
     };
+    auto le = [&](Off po, int k) -> T { return bload(T(), re, po.v, po.s + (unsigned)k * cstride); };
     auto U = [&](int k, Off o, Off po) -> T {
         T v = ld(ru, o, k);
-        if (MODE == SWEEP_PROLONG) v += bload(T(), re, po.v, po.s + (unsigned)k * cstride);
+        if (MODE == SWEEP_PROLONG) v += le(po, k);
         return v;
     };
 
 
     ChunkState<T, M> cs[CPW];
     T su[CPW][M];
-    T u_dn[CPW], u_c[CPW], wD[CPW];
+    T u_dn[CPW], u_c[CPW], wD[CPW], e_c[CPW];
     int k0[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         k0[c] = (c * P + p) * M;
-        u_dn[c] = u_c[c] = wD[c] = T(0);
+        u_dn[c] = u_c[c] = wD[c] = e_c[c] = T(0);
         if (k0[c] < nz) {
             if (k0[c] > 0) {
                 wD[c] = L.wz[k0[c] - 1] * ld(rU, C, k0[c] - 1);
                 if (MODE != SWEEP_ZERO) u_dn[c] = U(k0[c] - 1, C, PC);
             }
-            if (MODE != SWEEP_ZERO) u_c[c] = U(k0[c], C, PC);
+            if constexpr (XP) {
+                e_c[c] = le(PC, k0[c]);
+                u_c[c] = ld(ru, C, k0[c]) + e_c[c];
+            } else if (MODE != SWEEP_ZERO) {
+                u_c[c] = U(k0[c], C, PC);
+            }
         }
         cs[c].init();
     }
 
+    // The cells of a step are guarded by k < nz (a branch; loads are not moved
+    // across it, so each step waits for its own loads).  FULL (every chunk
+    // lies inside the column) drops the guards, and the scheduler issues the
+    // next cells' loads early.  The host selects it for the FP32 sweep from
+    // zero, whose 6 loads per cell left too few in flight (1024^2 x 128:
+    // 0.476 vs 0.500 ms).  The sweeps that read u (10-13 loads per cell) and
+    // the FP64 sweeps were slower unguarded (general 0.80 vs 0.63 ms,
+    // prolongation 0.93 vs 0.78 ms, FP64 from zero 1.15 vs 1.03 ms): with
+    // every cell's loads issued at once a CU holds far more data in flight
+    // than its L1.
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         // loads of the CPW cells of this step (wave-uniform validity)
@@ -358,18 +421,33 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
             const int k = k0[c] + t;
-            if (k < nz) {
+            if (FULL || k < nz) {
                 R[c].b = ld1(rb, C, k);
                 R[c].cE = ld(rE, C, k);
                 R[c].cEw = ld(rE, W, k);
                 R[c].cN = ld(rN, C, k);
                 R[c].cNs = ld(rN, Sx, k);
                 R[c].cU = ld1(rU, C, k);
-                R[c].uup = R[c].uE = R[c].uW = R[c].uN = R[c].uS = T(0);
-                if (MODE != SWEEP_ZERO) {
-                    if (k + 1 < nz) R[c].uup = U(k + 1, C, PC);
-                    R[c].uE = U(k, E, PE);
-                    R[c].uW = U(k, W, PW);
+                R[c].uup = R[c].uE = R[c].uW = R[c].uN = R[c].uS = R[c].eup = T(0);
+                // inside a full chunk only its last cell can be the top
+                const bool up = (FULL && t + 1 < M) || k + 1 < nz;
+                if constexpr (XP) {
+                    if (up) {
+                        R[c].eup = le(PC, k + 1);
+                        R[c].uup = ld(ru, C, k + 1) + R[c].eup;
+                    }
+                    R[c].uE = U(k, X, PX);
+                    const T eo = le(PO, k);
+                    R[c].uN = ld(ru, N, k) + (jodd ? eo : e_c[c]);
+                    R[c].uS = ld(ru, Sx, k) + (jodd ? e_c[c] : eo);
+                } else if (MODE != SWEEP_ZERO) {
+                    if (up) R[c].uup = U(k + 1, C, PC);
+                    if constexpr (XL) {
+                        R[c].uE = U(k, X, PX);
+                    } else {
+                        R[c].uE = U(k, E, PE);
+                        R[c].uW = U(k, W, PW);
+                    }
                     R[c].uN = U(k, N, PN);
                     R[c].uS = U(k, Sx, PS);
                 }
@@ -379,7 +457,7 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
             const int k = k0[c] + t;
-            if (k < nz) {
+            if (FULL || k < nz) {
                 const T h = L.wh[k];
                 const T mu = L.mu[k];
                 const T wE = h * R[c].cE;
@@ -391,7 +469,13 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
                 const T uc = u_c[c];
                 T r = R[c].b;
                 if (MODE != SWEEP_ZERO) {
-                    const T Hu = mu * uc + wE * (uc - R[c].uE) + wW * (uc - R[c].uW) + wN * (uc - R[c].uN) +
+                    T uE = R[c].uE, uW = R[c].uW;
+                    if constexpr (XL) {
+                        // R.uE holds the value across the tile edge (lanes 0, 63)
+                        uW = lane_from_prev(R[c].uE, uc);
+                        uE = lane_from_next(R[c].uE, uc);
+                    }
+                    const T Hu = mu * uc + wE * (uc - uE) + wW * (uc - uW) + wN * (uc - R[c].uN) +
                                  wS * (uc - R[c].uS) + wU * (uc - R[c].uup) + wD[c] * (uc - u_dn[c]);
                     r -= Hu;
                 }
@@ -399,6 +483,7 @@ __global__ __launch_bounds__(LB, (sweep_min_waves<T, M, CPW, MODE, LB>())) void 
                 su[c][t] = uc;
                 u_dn[c] = uc;
                 u_c[c] = R[c].uup;
+                if constexpr (XP) e_c[c] = R[c].eup;
                 wD[c] = wU;
             } else {
                 cs[c].identity(t);
@@ -566,8 +651,9 @@ __global__ __launch_bounds__(kStreamThreads) void k_resid_restrict(Level<T> L, c
 // KC levels; each lane streams its fine column, forming r = b - H u cell by
 // cell (every load a contiguous segment), adds the horizontal child pair by
 // a lane exchange, and wavefront 0 adds row 2J+1's pair sums from LDS and
-// writes the 32 coarse values of the tile per level.
-template <typename T, int KC, int CP>
+// writes the 32 coarse values of the tile per level.  XL: the east / west
+// values of u come from the neighbouring lanes (one load at the tile edges).
+template <typename T, int KC, int CP, bool XL>
 __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T *__restrict__ u,
                                                              const T *__restrict__ b, T *__restrict__ bc)
 {
@@ -593,6 +679,7 @@ __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T
         wD = L.wz[k0 - 1] * bload(T(), R.rU, R.oc, sm);
     }
     T uc = bload(T(), ru, R.oc, (unsigned)k0 * R.pstride);
+    const unsigned ox = lane == 0 ? R.ow : (lane == 63 ? R.oe : R.oc);
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
         const int k = k0 + q;
@@ -602,8 +689,17 @@ __global__ __launch_bounds__(128) void k_resid_restrict_rows(Level<T> L, const T
             const T up = (k + 1 < nz) ? bload(T(), ru, R.oc, sk + R.pstride) : T(0);
             const T h = L.wh[k];
             const T wU = L.wz[k] * bload<CP>(T(), R.rU, R.oc, sk);
-            const T hu = L.mu[k] * uc + h * bload(T(), R.rE, R.oc, sk) * (uc - bload(T(), ru, R.oe, sk)) +
-                         h * bload(T(), R.rE, R.ow, sk) * (uc - bload(T(), ru, R.ow, sk)) +
+            T uE, uW;
+            if constexpr (XL) {
+                const T ux = bload(T(), ru, ox, sk);
+                uE = lane_from_next(ux, uc);
+                uW = lane_from_prev(ux, uc);
+            } else {
+                uE = bload(T(), ru, R.oe, sk);
+                uW = bload(T(), ru, R.ow, sk);
+            }
+            const T hu = L.mu[k] * uc + h * bload(T(), R.rE, R.oc, sk) * (uc - uE) +
+                         h * bload(T(), R.rE, R.ow, sk) * (uc - uW) +
                          h * bload(T(), R.rN, R.oc, sk) * (uc - bload(T(), ru, R.on, sk)) +
                          h * bload(T(), R.rN, R.os, sk) * (uc - bload(T(), ru, R.os, sk)) + wU * (uc - up) +
                          wD * (uc - um);
@@ -841,7 +937,10 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // levels in flight at 80 VGPRs (6 wavefronts per SIMD) instead of one at
 // 54 (8 per SIMD); 1.45 vs 1.74 ms at 1024^2 x 128 with FP32 z.
 // CP: cache policy of c_U and of the p, q stores (read or written once).
-template <int KC, typename ZT, int CP>
+// XL (rows of whole tiles): p_new at the east / west neighbours comes from
+// the neighbouring lanes, formed there by the same expression (one pair of
+// loads at the tile edges instead of two pairs per cell).
+template <int KC, typename ZT, int CP, bool XL>
 __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const ZT *__restrict__ zt,
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
@@ -872,15 +971,25 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
         ZT zE, zW, zN, zS, zu;
         double pE, pW, pN, pS, pu, cE, cEw, cN, cNs, cU;
     };
+    const int lane = threadIdx.x & 63;
+    const unsigned ox = lane == 0 ? R.ow : (lane == 63 ? R.oe : R.oc);
     auto load = [&](int k) {
         Raw w;
         const unsigned sk = (unsigned)k * R.pstride;
-        w.zE = ZL(k, R.oe);
-        w.zW = ZL(k, R.ow);
+        if constexpr (XL) {
+            // the value across the tile edge (lanes 0 and 63)
+            w.zE = ZL(k, ox);
+            w.pE = PL(k, ox);
+            w.zW = ZT(0);
+            w.pW = 0.0;
+        } else {
+            w.zE = ZL(k, R.oe);
+            w.zW = ZL(k, R.ow);
+            w.pE = PL(k, R.oe);
+            w.pW = PL(k, R.ow);
+        }
         w.zN = ZL(k, R.on);
         w.zS = ZL(k, R.os);
-        w.pE = PL(k, R.oe);
-        w.pW = PL(k, R.ow);
         w.pN = PL(k, R.on);
         w.pS = PL(k, R.os);
         w.cE = bload(double(), R.rE, R.oc, sk);
@@ -916,8 +1025,17 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             const double pp = comb(cur.zu, cur.pu);
             const double h = L.wh[k];
             const double wU = L.wz[k] * cur.cU;
-            const double qq = L.mu[k] * pc + h * cur.cE * (pc - comb(cur.zE, cur.pE)) +
-                              h * cur.cEw * (pc - comb(cur.zW, cur.pW)) + h * cur.cN * (pc - comb(cur.zN, cur.pN)) +
+            double pE, pW;
+            if constexpr (XL) {
+                const double px = comb(cur.zE, cur.pE);
+                pE = lane_from_next(px, pc);
+                pW = lane_from_prev(px, pc);
+            } else {
+                pE = comb(cur.zE, cur.pE);
+                pW = comb(cur.zW, cur.pW);
+            }
+            const double qq = L.mu[k] * pc + h * cur.cE * (pc - pE) +
+                              h * cur.cEw * (pc - pW) + h * cur.cN * (pc - comb(cur.zN, cur.pN)) +
                               h * cur.cNs * (pc - comb(cur.zS, cur.pS)) + wU * (pc - pp) + wD * (pc - pm);
             bstore<CP>(pc, rpn, oo, sk);
             bstore<CP>(qq, rq, oo, sk);
@@ -1157,6 +1275,32 @@ bool nt_level(const Level<T> &L)
     return (size_t)L.plane * L.nz >= ((size_t)1 << 24);
 }
 
+// Small FP32 levels fill few CUs and are bound by the latency of each
+// thread's chain of cells along k (1024^2 x 128, V-cycle 4.24 vs 4.27 ms
+// with both):
+//  - below 2^24 cells (levels 2-6) the restriction walks 4-level chunks
+//    instead of 16 (TPMG_SHORT_RESTRICT_CELLS overrides the bound);
+//  - below 2^22 cells (levels 3-6) every sweep walks its full chunks
+//    unguarded (TPMG_LAT_CELLS overrides the bound).
+template <typename T>
+bool small_level(const Level<T> &L, int env_cells, int log2_cells)
+{
+    const double bound = env_cells >= 0 ? (double)env_cells : (double)((size_t)1 << log2_cells);
+    return sizeof(T) == 4 && (double)L.plane * L.nz < bound;
+}
+template <typename T>
+bool lat_level(const Level<T> &L)
+{
+    static const int e = env_int("TPMG_LAT_CELLS");
+    return small_level(L, e, 22);
+}
+template <typename T>
+bool short_restrict_level(const Level<T> &L)
+{
+    static const int e = env_int("TPMG_SHORT_RESTRICT_CELLS");
+    return small_level(L, e, 24);
+}
+
 // k-chunk of a streaming kernel: `dflt` unless TPMG_KCHUNK overrides it.
 // Measured on 1024^2 x 128: longer chunks help the FP64 CG stencils (64
 // cells: 1.68 vs 1.77 ms) and the finest restriction (32: 0.685 vs 0.70 ms);
@@ -1206,9 +1350,15 @@ hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, 
     // 8 instead of 16 bytes of spill) and cost about 1 % elsewhere, so by
     // default only that sweep uses them (TPMG_SWEEP_ROWS=1: every sweep that
     // can, 0: none).
-    static const int erows = env_int("TPMG_SWEEP_ROWS");
+    static const int erows = env_int("TPMG_SWEEP_ROWS"), exl = env_int("TPMG_SWEEP_XL");
     const bool fits = L.n % 64 == 0 && (mode != SWEEP_PROLONG || L.n % 128 == 0);
     const bool rows = fits && (erows == 1 || (erows < 0 && sizeof(T) == 4 && mode == SWEEP_PROLONG));
+    // East / west values of u by lane exchange wherever the rows are whole
+    // tiles (TPMG_SWEEP_XL=0: loads as elsewhere).  Measured at 1024^2 x 128:
+    // FP32 V-cycle 4.32 vs 4.36-4.39 ms; the FP32 prolongation sweep then
+    // fits its 64-VGPR bound without spill.
+    const bool xl = fits && mode != SWEEP_ZERO && exl != 0;
+    const int rm = xl ? 2 : (rows ? 1 : 0);
     // Non-temporal accesses for b, c_U and the output on levels too large
     // for the caches (TPMG_SWEEP_NT=0: plain everywhere, 1: everywhere):
     // measured at 1024^2 x 128, FP32 V-cycle 4.36 vs 4.51 ms; on levels whose
@@ -1216,28 +1366,38 @@ hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, 
     // hits that the hints would give away.
     static const int ent = env_int("TPMG_SWEEP_NT");
     const bool nt = ent == 1 || (ent != 0 && nt_level(L));
+    // Unguarded chunks (every chunk inside the column) for the FP32 sweep from
+    // zero and for every FP32 sweep on a latency-bound level.
+    const bool chunks_full = L.full_chunks && L.nz % (M * CPW) == 0;
     auto go = [&](auto mc, auto rc) {
-        if (nt)
-            hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value, kNT>), dim3(tiles),
-                               block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
-        else
-            hipLaunchKernelGGL((k_sweep<T, M, CPW, decltype(mc)::value, LB, decltype(rc)::value, 0>), dim3(tiles),
-                               block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
+        constexpr int MC = decltype(mc)::value, RC = decltype(rc)::value;
+        auto launch = [&](auto cp, auto fl) {
+            hipLaunchKernelGGL((k_sweep<T, M, CPW, MC, LB, RC, decltype(cp)::value, decltype(fl)::value>),
+                               dim3(tiles), block, lds, s, L, u, b, out, ec, omega, tbi, tbj);
+        };
+        using CNT = std::integral_constant<int, kNT>;
+        using C0 = std::integral_constant<int, 0>;
+        if constexpr (MC == SWEEP_ZERO && sizeof(T) == 4) {
+            if (chunks_full) return nt ? launch(CNT(), std::true_type()) : launch(C0(), std::true_type());
+        } else if constexpr (sizeof(T) == 4) {
+            if (chunks_full && lat_level(L)) return launch(C0(), std::true_type());
+        }
+        nt ? launch(CNT(), std::false_type()) : launch(C0(), std::false_type());
     };
-    using RT = std::true_type;
-    using RF = std::false_type;
+    using R0 = std::integral_constant<int, 0>;
+    using R1 = std::integral_constant<int, 1>;
+    using R2 = std::integral_constant<int, 2>;
+    auto by_rm = [&](auto mc) {
+        if (rm == 2) go(mc, R2());
+        else if (rm == 1) go(mc, R1());
+        else go(mc, R0());
+    };
     switch (mode) {
     case SWEEP_ZERO:
-        rows ? go(std::integral_constant<int, SWEEP_ZERO>(), RT()) : go(std::integral_constant<int, SWEEP_ZERO>(), RF());
+        rm ? go(std::integral_constant<int, SWEEP_ZERO>(), R1()) : go(std::integral_constant<int, SWEEP_ZERO>(), R0());
         break;
-    case SWEEP_GENERAL:
-        rows ? go(std::integral_constant<int, SWEEP_GENERAL>(), RT())
-             : go(std::integral_constant<int, SWEEP_GENERAL>(), RF());
-        break;
-    default:
-        rows ? go(std::integral_constant<int, SWEEP_PROLONG>(), RT())
-             : go(std::integral_constant<int, SWEEP_PROLONG>(), RF());
-        break;
+    case SWEEP_GENERAL: by_rm(std::integral_constant<int, SWEEP_GENERAL>()); break;
+    default: by_rm(std::integral_constant<int, SWEEP_PROLONG>()); break;
     }
     return hipGetLastError();
 }
@@ -1313,21 +1473,39 @@ template <typename T>
 hipError_t launch_resid_restrict(const Level<T> &L, const T *u, const T *b, T *bc, hipStream_t s)
 {
     // Rows of whole tiles, FP32: the row-tile kernel (1024^2 x 128: 0.58 vs
-    // 0.69 ms).  In FP64 it was slower (1.29 vs 1.21 ms) and is not used.
-    if ((L.n & 63) == 0 && sizeof(T) == 4) {
-        const int kc = 16, nkc = (L.nz + kc - 1) / kc;
+    // 0.69 ms).  In FP64 it was slower (1.29 vs 1.21 ms) and is not used
+    // (TPMG_RESTRICT_ROWS64=1 selects it).
+    static const int er64 = env_int("TPMG_RESTRICT_ROWS64");
+    if ((L.n & 63) == 0 && (sizeof(T) == 4 || er64 == 1)) {
+        const bool short_chunks = short_restrict_level(L);
+        const int kc = short_chunks ? 4 : 16, nkc = (L.nz + kc - 1) / kc;
         const int grid = nkc * (L.n / 2) * (L.n / 64);
-        // non-temporal b, c_U and output, as in the sweep (TPMG_RESTRICT_NT=0: plain)
-        static const int ent = env_int("TPMG_RESTRICT_NT");
-        if (ent == 1 || (ent != 0 && nt_level(L)))
-            hipLaunchKernelGGL((k_resid_restrict_rows<T, 16, kNT>), dim3(grid), dim3(128), 0, s, L, u, b, bc);
-        else
-            hipLaunchKernelGGL((k_resid_restrict_rows<T, 16, 0>), dim3(grid), dim3(128), 0, s, L, u, b, bc);
+        // non-temporal b, c_U and output, as in the sweep (TPMG_RESTRICT_NT=0:
+        // plain); east / west values of u by lane exchange (TPMG_RESTRICT_XL=0: loads)
+        static const int ent = env_int("TPMG_RESTRICT_NT"), exl = env_int("TPMG_RESTRICT_XL");
+        const bool nt = ent == 1 || (ent != 0 && nt_level(L)), xl = exl != 0;
+        auto go = [&](auto kcc, auto cp, auto x) {
+            hipLaunchKernelGGL((k_resid_restrict_rows<T, decltype(kcc)::value, decltype(cp)::value,
+                                                      decltype(x)::value>),
+                               dim3(grid), dim3(128), 0, s, L, u, b, bc);
+        };
+        using K16 = std::integral_constant<int, 16>;
+        using NT = std::integral_constant<int, kNT>;
+        using PL = std::integral_constant<int, 0>;
+        using Y = std::true_type;
+        using F = std::false_type;
+        if (nt) {
+            xl ? go(K16(), NT(), Y()) : go(K16(), NT(), F());
+        } else if (short_chunks) {
+            go(std::integral_constant<int, 4>(), PL(), Y());
+        } else {
+            xl ? go(K16(), PL(), Y()) : go(K16(), PL(), F());
+        }
         return hipGetLastError();
     }
     const int planec = (L.n / 2) * (L.n / 2);
     const int ncb = (planec + kStreamThreads - 1) / kStreamThreads;
-    const int kc = stream_kc(planec >= 512 * 512 && L.nz >= 32 ? 32 : 16);
+    const int kc = short_restrict_level(L) ? 4 : stream_kc(planec >= 512 * 512 && L.nz >= 32 ? 32 : 16);
     const int nkc = (L.nz + kc - 1) / kc;
     return with_kc(kc, [&](auto KCc) {
         hipLaunchKernelGGL((k_resid_restrict<T, decltype(KCc)::value>), dim3(ncb * nkc), dim3(kStreamThreads), 0, s,
@@ -1467,21 +1645,31 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     *nblocks_out = G;
     // Non-temporal c_U and p, q stores on levels larger than the caches
     // (TPMG_CG_NT=0: never, 1: always): 1.39 vs 1.45 ms at 1024^2 x 128.
-    static const int ent = env_int("TPMG_CG_NT");
+    // East / west neighbours by lane exchange where the rows are whole tiles
+    // (16-level chunks only; TPMG_CG_XL=0: loads).
+    static const int ent = env_int("TPMG_CG_NT"), exl = env_int("TPMG_CG_XL");
     const bool nt = ent == 1 || (ent != 0 && nt_level(L));
+    const bool xl = exl != 0 && (L.n & 63) == 0;
     return with_kc(kc, [&](auto KCc) {
         constexpr int K = decltype(KCc)::value;
-        auto go = [&](auto cp) {
+        auto go = [&](auto cp, auto x) {
             constexpr int CP = decltype(cp)::value;
+            constexpr bool XL = decltype(x)::value;
             if (z32)
-                hipLaunchKernelGGL((k_pcg_apply<K, float, CP>), dim3(G), dim3(kStreamThreads), 0, s, L, z32, p_old,
-                                   p_new, q, sc, first, partials);
+                hipLaunchKernelGGL((k_pcg_apply<K, float, CP, XL>), dim3(G), dim3(kStreamThreads), 0, s, L, z32,
+                                   p_old, p_new, q, sc, first, partials);
             else
-                hipLaunchKernelGGL((k_pcg_apply<K, double, CP>), dim3(G), dim3(kStreamThreads), 0, s, L, z, p_old,
-                                   p_new, q, sc, first, partials);
+                hipLaunchKernelGGL((k_pcg_apply<K, double, CP, XL>), dim3(G), dim3(kStreamThreads), 0, s, L, z,
+                                   p_old, p_new, q, sc, first, partials);
         };
-        if (nt) go(std::integral_constant<int, kNT>());
-        else go(std::integral_constant<int, 0>());
+        auto by_xl = [&](auto cp) {
+            if constexpr (K == 16) {
+                if (xl) return go(cp, std::true_type());
+            }
+            go(cp, std::false_type());
+        };
+        if (nt) by_xl(std::integral_constant<int, kNT>());
+        else by_xl(std::integral_constant<int, 0>());
         return hipGetLastError();
     });
 }
