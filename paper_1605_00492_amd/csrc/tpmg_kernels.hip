@@ -1213,7 +1213,8 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
 
 // dJ/dc_f = -gamma_f (lambda_p - lambda_q)(x_p - x_q) on level-0 faces.
 // NT: the gradient (written once, never read back here) with non-temporal
-// stores.
+// stores.  (Unrolling a full chunk without guards was slower, 1.29 vs
+// 1.22 ms at 1024^2 x 128; the east value by lane exchange gained 0.5 %.)
 template <int KC, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> L,
                                                                   const double *__restrict__ lam,
@@ -1249,6 +1250,58 @@ __global__ __launch_bounds__(kStreamThreads) void k_face_gradient(Level<double> 
                 g[2 * fstride + o + col] = gU;
             }
         }
+        lc = lu;
+        xc = xu;
+    }
+}
+
+// The same gradient with two columns per thread and 16-byte accesses (rows
+// of whole 128-column segments, 16-byte aligned arrays): thread = (column
+// pair, chunk of KC levels); the east value of the pair's second column comes
+// from the next lane (one load at the segment edge).  1024^2 x 128: 1.115 vs
+// 1.22 ms for one column per thread.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+template <int KC>
+__global__ __launch_bounds__(kStreamThreads) void k_face_gradient2(Level<double> L,
+                                                                   const double *__restrict__ lam,
+                                                                   const double *__restrict__ x,
+                                                                   double *__restrict__ g)
+{
+    const int nz = L.nz, plane = L.plane, n = L.n;
+    const int npairs = plane >> 1, ncb = npairs / kStreamThreads;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int kc = blk / ncb, cb = blk % ncb;
+    const int pr = cb * kStreamThreads + threadIdx.x;
+    const int col = 2 * pr, k0 = kc * KC;
+    const int i = col % n, j = col / n;
+    const int ce = (i + 2 == n) ? col + 2 - n : col + 2;           // east of the second column
+    const int cn = (j + 1 == n) ? col + n - plane : col + n;       // north of both
+    const int lane = threadIdx.x & 63;
+    const int cx = lane == 63 ? ce : col;
+    const size_t fstride = (size_t)nz * plane;
+    auto ld2 = [](const double *a, size_t o) { return *reinterpret_cast<const dbl2 *>(a + o); };
+    dbl2 lc = ld2(lam, (size_t)k0 * plane + col), xc = ld2(x, (size_t)k0 * plane + col);
+    for (int t = 0; t < KC; ++t) {
+        const int k = k0 + t;
+        if (k >= nz) break;
+        const size_t o = (size_t)k * plane;
+        const double h = L.wh[k];
+        const bool up = k + 1 < nz;
+        const dbl2 lu = up ? ld2(lam, o + plane + col) : dbl2{0.0, 0.0};
+        const dbl2 xu = up ? ld2(x, o + plane + col) : dbl2{0.0, 0.0};
+        const dbl2 ln = ld2(lam, o + cn), xn = ld2(x, o + cn);
+        const double le = lane_from_next(lam[o + cx], lc.x), xe = lane_from_next(x[o + cx], xc.x);
+        dbl2 gE, gN, gU;
+        gE.x = -h * (lc.x - lc.y) * (xc.x - xc.y);
+        gE.y = -h * (lc.y - le) * (xc.y - xe);
+        gN.x = -h * (lc.x - ln.x) * (xc.x - xn.x);
+        gN.y = -h * (lc.y - ln.y) * (xc.y - xn.y);
+        const double wz = L.wz[k];
+        gU.x = up ? -wz * (lc.x - lu.x) * (xc.x - xu.x) : 0.0;
+        gU.y = up ? -wz * (lc.y - lu.y) * (xc.y - xu.y) : 0.0;
+        __builtin_nontemporal_store(gE, reinterpret_cast<dbl2 *>(g + o + col));
+        __builtin_nontemporal_store(gN, reinterpret_cast<dbl2 *>(g + fstride + o + col));
+        __builtin_nontemporal_store(gU, reinterpret_cast<dbl2 *>(g + 2 * fstride + o + col));
         lc = lu;
         xc = xu;
     }
@@ -1731,11 +1784,23 @@ hipError_t launch_finalize(const double *partials, int nblocks, int nvals, Scala
 hipError_t launch_face_gradient(const Level<double> &L, const double *lam, const double *x, double *g,
                                 hipStream_t s)
 {
-    // Measured at 1024^2 x 128: non-temporal stores and 64-cell chunks 1.218 ms,
-    // plain stores 1.266 ms (64) / 1.328 ms (16 cells); TPMG_FG_NT=0 restores
-    // plain stores.  Planes below 512^2 keep 16-cell chunks (more workgroups).
+    // Measured at 1024^2 x 128 (one column per thread): non-temporal stores
+    // and 64-cell chunks 1.218 ms, plain stores 1.266 ms (64) / 1.328 ms (16
+    // cells); TPMG_FG_NT=0 restores plain stores.  Planes below 512^2 keep
+    // 16-cell chunks (more workgroups).  Two columns per thread where the
+    // rows and the arrays allow it (TPMG_FG_WIDE=0: one).
     const int kc = stream_kc(L.plane >= (1 << 18) ? 64 : 16);
-    static const int nt = env_int("TPMG_FG_NT");
+    static const int nt = env_int("TPMG_FG_NT"), ew = env_int("TPMG_FG_WIDE");
+    const bool aligned = ((uintptr_t)lam | (uintptr_t)x | (uintptr_t)g) % 16 == 0;
+    if (ew != 0 && nt != 0 && aligned && L.n % 128 == 0 && (L.plane / 2) % kStreamThreads == 0) {
+        const int nkc = (L.nz + kc - 1) / kc;
+        const int grid = nkc * (L.plane / 2 / kStreamThreads);
+        return with_kc(kc, [&](auto KCc) {
+            hipLaunchKernelGGL((k_face_gradient2<decltype(KCc)::value>), dim3(grid), dim3(kStreamThreads), 0, s, L,
+                               lam, x, g);
+            return hipGetLastError();
+        });
+    }
     return with_kc(kc, [&](auto KCc) {
         if (nt != 0)
             hipLaunchKernelGGL((k_face_gradient<decltype(KCc)::value, true>), dim3(stream_grid(L, kc)),
