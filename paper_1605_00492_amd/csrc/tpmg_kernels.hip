@@ -966,7 +966,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
     auto PL = [&](int k, unsigned o) -> double {
         return first ? 0.0 : bload(double(), rp, o, (unsigned)k * R.pstride);
     };
-    auto comb = [&](ZT zz, double pp) -> double { return first ? (double)zz : (double)zz + beta * pp; };
+    // Explicit fused multiply-adds in a fixed order: every form of the kernel
+    // (lane exchange or loads) then rounds identically, whatever the
+    // compiler would contract.
+    auto comb = [&](ZT zz, double pp) -> double { return first ? (double)zz : __builtin_fma(beta, pp, (double)zz); };
     struct Raw {
         ZT zE, zW, zN, zS, zu;
         double pE, pW, pN, pS, pu, cE, cEw, cN, cNs, cU;
@@ -1011,8 +1014,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
         pm = comb(ZL(k0 - 1, R.oc), PL(k0 - 1, R.oc));
         wD = L.wz[k0 - 1] * bload(double(), R.rU, R.oc, (unsigned)(k0 - 1) * R.pstride);
     }
-    const double zc = (double)ZL(k0, R.oc);
-    double pc = first ? zc : zc + beta * PL(k0, R.oc);
+    double pc = comb(ZL(k0, R.oc), PL(k0, R.oc));
     double acc_pq = 0;
     Raw cur = load(k0);
 #pragma unroll
@@ -1034,9 +1036,13 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
                 pE = comb(cur.zE, cur.pE);
                 pW = comb(cur.zW, cur.pW);
             }
-            const double qq = L.mu[k] * pc + h * cur.cE * (pc - pE) +
-                              h * cur.cEw * (pc - pW) + h * cur.cN * (pc - comb(cur.zN, cur.pN)) +
-                              h * cur.cNs * (pc - comb(cur.zS, cur.pS)) + wU * (pc - pp) + wD * (pc - pm);
+            double qq = L.mu[k] * pc;
+            qq = __builtin_fma(h * cur.cE, pc - pE, qq);
+            qq = __builtin_fma(h * cur.cEw, pc - pW, qq);
+            qq = __builtin_fma(h * cur.cN, pc - comb(cur.zN, cur.pN), qq);
+            qq = __builtin_fma(h * cur.cNs, pc - comb(cur.zS, cur.pS), qq);
+            qq = __builtin_fma(wU, pc - pp, qq);
+            qq = __builtin_fma(wD, pc - pm, qq);
             bstore<CP>(pc, rpn, oo, sk);
             bstore<CP>(qq, rq, oo, sk);
             if (active) acc_pq += pc * qq;

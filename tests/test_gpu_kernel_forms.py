@@ -1,0 +1,133 @@
+"""Alternative forms of the same kernels give the same results.
+
+Several kernels have forms that differ only in how they obtain their
+operands or how they walk a column, never in the arithmetic:
+  - the sweep's row-uniform addressing (TPMG_SWEEP_ROWS), where the rows of
+    a level are whole 64-column tiles;
+  - east / west values of u (of p_new in the CG direction update) taken
+    from the neighbouring lane instead of loaded (TPMG_SWEEP_XL,
+    TPMG_RESTRICT_XL, TPMG_CG_XL);
+  - 4-level restriction chunks on small levels (TPMG_SHORT_RESTRICT_CELLS);
+  - the two-column face gradient with 16-byte accesses (TPMG_FG_WIDE).
+These must agree bit for bit.  The unguarded full-chunk FP32 sweeps
+(TPMG_FULL_CHUNKS, TPMG_LAT_CELLS) compute the same expressions, but with a
+chunk's cells in one basic block the compiler contracts their FP32
+multiply-adds differently, so they agree to FP32 rounding only: measured
+against the FP64 run of the same (FP32-representable) inputs, their error
+stays within the FP32 bound of the component parity tests, max(2e-5, twice
+the guarded form's error), and the mixed solve within 1e-8 of the FP64
+solve.  FP64 has no unguarded form and stays bit-exact.
+
+The same seeded inputs run in child processes with every alternative off
+("plain"), with all but the unguarded chunks on ("exchange"), with row
+addressing everywhere but no lane exchange ("rows"), and with the defaults.
+nz = 13 leaves a ragged last chunk (no unguarded form applies); nz = 16 runs
+the full-chunk and small-level forms (512^2 x 16 has 2^22 cells: its finest
+level takes the large-level forms, the coarser ones the small-level forms).
+"""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import device, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, {root!r})
+import paper_1605_00492_amd as tp
+n, nz, levels = {n}, {nz}, 3
+rng = np.random.default_rng(1605)
+c = 1.0 + 0.5 * rng.random((3, nz, n, n))
+dz = [1.05 ** k for k in range(nz)]
+dev = torch.device("cuda:0")
+H = {{p: tp.Hierarchy(torch.from_numpy(c).to(dev), dz=dz, a_h=4.0, a_z=1e4, levels=levels, precision=p)
+     for p in ("fp64", "mixed")}}
+DT = {{"fp64": torch.float64, "mixed": torch.float32}}
+# inputs representable in FP32, so that the FP64 run is the reference of the FP32 one
+vec = lambda l: torch.from_numpy(rng.standard_normal((nz, n >> l, n >> l)).astype(np.float32).astype(np.float64)).to(dev)
+out = {{}}
+for l in range(levels):
+    b, u = vec(l), vec(l)
+    e = vec(l + 1) if l + 1 < levels else None
+    for p, h in H.items():
+        cv = lambda t: t.to(DT[p])
+        out[f"{{p}}_zero_{{l}}"] = h.smooth(cv(b), level=l)
+        out[f"{{p}}_general_{{l}}"] = h.smooth(cv(b), cv(u), level=l)
+        if e is not None:
+            out[f"{{p}}_prolong_{{l}}"] = h.prolong_smooth(cv(u), cv(e), cv(b), level=l)
+            out[f"{{p}}_restrict_{{l}}"] = h.residual_restrict(cv(u), cv(b), level=l)
+r = vec(0)
+for p, h in H.items():
+    out[f"{{p}}_vcycle"] = h.vcycle(r.to(DT[p]))
+b64 = vec(0)
+for p, h in H.items():
+    x, info = h.solve(b64, rtol=1e-9)
+    out[f"{{p}}_solve"] = x
+    out[f"{{p}}_solve_iterations"] = torch.tensor([info["iterations"]])
+out["face_gradient"] = H["fp64"].face_gradient(vec(0), out["fp64_solve"])
+torch.cuda.synchronize()
+for h in H.values():
+    h.close()
+np.savez({path!r}, **{{k: v.cpu().numpy() for k, v in out.items()}})
+print("child ok", flush=True)
+"""
+
+PLAIN = dict(TPMG_SWEEP_ROWS="0", TPMG_SWEEP_XL="0", TPMG_RESTRICT_XL="0", TPMG_CG_XL="0",
+             TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0", TPMG_SHORT_RESTRICT_CELLS="0", TPMG_FG_WIDE="0")
+SETTINGS = {
+    "plain": PLAIN,
+    "exchange": dict(TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0"),
+    "rows": dict(TPMG_SWEEP_ROWS="1", TPMG_SWEEP_XL="0", TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0"),
+    "default": {},
+}
+ULP32 = 2.0 ** -23
+
+
+def _run(tmp_path, n, nz, name):
+    path = str(tmp_path / f"forms_{n}_{nz}_{name}.npz")
+    env = {k: v for k, v in os.environ.items() if not k.startswith("TPMG_")}
+    env.update(SETTINGS[name])
+    print(f"[gpu] kernel forms child n={n} nz={nz} setting={name} {SETTINGS[name]}", flush=True)
+    r = subprocess.run([sys.executable, "-c", CHILD.format(root=ROOT, path=path, n=n, nz=nz)], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    with np.load(path) as f:
+        return {k: f[k] for k in f.files}
+
+
+@pytest.mark.parametrize("n,nz", [(256, 13), (512, 16)])
+def test_kernel_forms_agree(tmp_path, n, nz):
+    device()
+    ref = _run(tmp_path, n, nz, "plain")
+    for name in ("exchange", "rows", "default"):
+        got = _run(tmp_path, n, nz, name)
+        assert sorted(got) == sorted(ref)
+        diff = [k for k in ref if not np.array_equal(got[k], ref[k])]
+        print(f"[gpu] {name} vs plain (n={n}, nz={nz}): {len(ref)} outputs, differing {json.dumps(diff)}",
+              flush=True)
+        if name != "default" or nz % 8:
+            assert not diff, diff
+            continue
+        # unguarded FP32 sweeps: FP32 outputs within the FP32 bound of the
+        # component parity tests, measured against the FP64 run of the same
+        # inputs (identical in every form); FP64 bit-exact
+        for k in diff:
+            assert k.startswith("mixed_"), k
+            if k == "mixed_solve_iterations":
+                continue
+            ref64 = ref["fp64_" + k[len("mixed_"):]]
+            e_plain, e_dflt = rel_err(ref[k], ref64), rel_err(got[k], ref64)
+            bound = 1e-8 if k == "mixed_solve" else max(2e-5, 2.0 * e_plain)
+            print(f"[gpu]   {k}: error vs FP64 {e_dflt:.2e} (guarded form {e_plain:.2e}, bound {bound:.1e})",
+                  flush=True)
+            assert e_dflt <= bound, (k, e_dflt, e_plain)
+        assert np.array_equal(got["mixed_solve_iterations"], ref["mixed_solve_iterations"])
