@@ -32,14 +32,22 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+        cmds.append([hipcc(), *FLAGS, "-c", src, "-o", obj])
+        objs.append(obj)
+    # the sources compile independently: one hipcc process each
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+        for f in [pool.submit(run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

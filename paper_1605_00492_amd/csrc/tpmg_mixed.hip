@@ -17,8 +17,6 @@
 //   (D^T x)_f = x_p - x_q,
 //   A (u, p)  = (M u - D^T p, D u + M3 p).
 // All kernels stream: thread = (column, chunk of KC cells along k).
-#include <cstdint>
-#include <initializer_list>
 #include <type_traits>
 
 #include "tpmg_device.h"
@@ -208,77 +206,34 @@ struct VecSet {
     double a[kMultiMax];
 };
 
-// The vector kernels read and write VW consecutive elements per thread:
-// VW = 2 (16-byte accesses, the width at which a plain copy runs fastest)
-// where the length is even and every vector 16-byte aligned, else 1.
-typedef double vd2 __attribute__((ext_vector_type(2)));
-template <int VW>
-__device__ __forceinline__ void vload(const double *__restrict__ p, size_t g, double (&a)[VW])
-{
-    if constexpr (VW == 2) {
-        const vd2 t = reinterpret_cast<const vd2 *>(p)[g];
-        a[0] = t.x;
-        a[1] = t.y;
-    } else {
-        a[0] = p[g];
-    }
-}
-template <int VW>
-__device__ __forceinline__ void vstore(double *__restrict__ p, size_t g, const double (&a)[VW])
-{
-    if constexpr (VW == 2) {
-        vd2 t;
-        t.x = a[0];
-        t.y = a[1];
-        reinterpret_cast<vd2 *>(p)[g] = t;
-    } else {
-        p[g] = a[0];
-    }
-}
-
 // partials[i * G + block] = block part of (w, v_i), i < NV.
-template <int NV, int VW>
+template <int NV>
 __global__ __launch_bounds__(256) void k_multidot(size_t n, const double *__restrict__ w, VecSet S,
                                                   double *__restrict__ partials)
 {
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    const size_t m = n / VW;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < m; g += (size_t)gridDim.x * 256) {
-        double wq[VW];
-        vload<VW>(w, g, wq);
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        const double wq = w[g];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double v[VW];
-            vload<VW>(S.v[i], g, v);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) acc[i] += wq[e] * v[e];
-        }
+        for (int i = 0; i < NV; ++i) acc[i] += wq * S.v[i][g];
     }
     block_partials<NV>(acc, partials, gridDim.x, blockIdx.x);
 }
 
 // y += sum_i a_i v_i; with partials, also the block parts of (y, y) afterwards.
-template <int NV, int VW>
+template <int NV>
 __global__ __launch_bounds__(256) void k_multiaxpy(size_t n, double *__restrict__ y, VecSet S,
                                                    double *__restrict__ partials)
 {
     double nrm = 0.0;
-    const size_t m = n / VW;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < m; g += (size_t)gridDim.x * 256) {
-        double s[VW];
-        vload<VW>(y, g, s);
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        double s = y[g];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double v[VW];
-            vload<VW>(S.v[i], g, v);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) s[e] += S.a[i] * v[e];
-        }
-        vstore<VW>(y, g, s);
-#pragma unroll
-        for (int e = 0; e < VW; ++e) nrm += s[e] * s[e];
+        for (int i = 0; i < NV; ++i) s += S.a[i] * S.v[i][g];
+        y[g] = s;
+        nrm += s * s;
     }
     if (partials) {
         double v[1] = {nrm};
@@ -288,31 +243,25 @@ __global__ __launch_bounds__(256) void k_multiaxpy(size_t n, double *__restrict_
 
 // y += sum_i a_i v_i, then the block parts of (y, v_i), i < NV, and (y, y):
 // the second Gram-Schmidt pass's dots ride on the first pass's update.
-template <int NV, int VW>
+template <int NV>
 __global__ __launch_bounds__(256) void k_multiaxpy_dot(size_t n, double *__restrict__ y, VecSet S,
                                                        double *__restrict__ partials)
 {
     double acc[NV + 1];
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-    const size_t m = n / VW;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < m; g += (size_t)gridDim.x * 256) {
-        double v[NV][VW];
-        double s[VW];
-        vload<VW>(y, g, s);
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        double v[NV];
+        double s = y[g];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vload<VW>(S.v[i], g, v[i]);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) s[e] += S.a[i] * v[i][e];
+            v[i] = S.v[i][g];
+            s += S.a[i] * v[i];
         }
-        vstore<VW>(y, g, s);
+        y[g] = s;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] += s[e] * v[i][e];
-            acc[NV] += s[e] * s[e];
-        }
+        for (int i = 0; i < NV; ++i) acc[i] += s * v[i];
+        acc[NV] += s * s;
     }
     block_partials<NV + 1>(acc, partials, gridDim.x, blockIdx.x);
 }
@@ -328,7 +277,7 @@ struct CorrSet {
     double ca[kMultiMax], cw[kMultiMax], sd[kMultiMax];
 };
 
-template <int NV, int VW>
+template <int NV>
 __global__ __launch_bounds__(256) void k_corr_axpy_dot(size_t n, double *__restrict__ u, double *__restrict__ w,
                                                        CorrSet S, double inv_rho, double hq,
                                                        double *__restrict__ partials)
@@ -336,34 +285,22 @@ __global__ __launch_bounds__(256) void k_corr_axpy_dot(size_t n, double *__restr
     double acc[NV + 2];
 #pragma unroll
     for (int i = 0; i < NV + 2; ++i) acc[i] = 0.0;
-    const size_t m = n / VW;
-    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < m; g += (size_t)gridDim.x * 256) {
-        double v[NV][VW];
-        double q[VW], y[VW];
-        vload<VW>(u, g, q);
-        vload<VW>(w, g, y);
-#pragma unroll
-        for (int e = 0; e < VW; ++e) q[e] *= inv_rho;
+    for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) {
+        double v[NV];
+        double q = u[g] * inv_rho, y = w[g];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vload<VW>(S.v[i], g, v[i]);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                q[e] -= S.ca[i] * v[i][e];
-                y[e] -= S.cw[i] * v[i][e];
-            }
+            v[i] = S.v[i][g];
+            q -= S.ca[i] * v[i];
+            y -= S.cw[i] * v[i];
         }
+        y -= hq * q;
+        u[g] = q;
+        w[g] = y;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) y[e] -= hq * q[e];
-        vstore<VW>(u, g, q);
-        vstore<VW>(w, g, y);
-#pragma unroll
-        for (int e = 0; e < VW; ++e) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] += S.sd[i] * v[i][e] * y[e];
-            acc[NV] += q[e] * y[e];
-            acc[NV + 1] += y[e] * y[e];
-        }
+        for (int i = 0; i < NV; ++i) acc[i] += S.sd[i] * v[i] * y;
+        acc[NV] += q * y;
+        acc[NV + 1] += y * y;
     }
     block_partials<NV + 2>(acc, partials, gridDim.x, blockIdx.x);
 }
@@ -394,61 +331,29 @@ __global__ __launch_bounds__(256) void k_sum_values(const double *__restrict__ p
     if (threadIdx.x == 0) out[v] = sh[0];
 }
 
-// 16-byte accesses: even length and every vector 16-byte aligned
-// (TPMG_VEC_WIDE=0: one element per thread).
-bool vec_wide(size_t n, std::initializer_list<const void *> ptrs)
+template <int NV>
+void launch_multidot_n(size_t n, const double *w, const VecSet &S, double *partials, int G, hipStream_t s)
 {
-    static const int e = env_int("TPMG_VEC_WIDE");
-    if (e == 0 || n % 2) return false;
-    for (const void *p : ptrs)
-        if (p && (uintptr_t)p % 16) return false;
-    return true;
-}
-bool vec_wide(size_t n, const VecSet &S, int nv, std::initializer_list<const void *> ptrs)
-{
-    if (!vec_wide(n, ptrs)) return false;
-    for (int i = 0; i < nv; ++i)
-        if ((uintptr_t)S.v[i] % 16) return false;
-    return true;
+    hipLaunchKernelGGL((k_multidot<NV>), dim3(G), dim3(256), 0, s, n, w, S, partials);
 }
 
 template <int NV>
-void launch_multidot_n(size_t n, const double *w, const VecSet &S, double *partials, int G, bool wide,
-                       hipStream_t s)
+void launch_multiaxpy_n(size_t n, double *y, const VecSet &S, double *partials, int G, hipStream_t s)
 {
-    if (wide)
-        hipLaunchKernelGGL((k_multidot<NV, 2>), dim3(G), dim3(256), 0, s, n, w, S, partials);
-    else
-        hipLaunchKernelGGL((k_multidot<NV, 1>), dim3(G), dim3(256), 0, s, n, w, S, partials);
+    hipLaunchKernelGGL((k_multiaxpy<NV>), dim3(G), dim3(256), 0, s, n, y, S, partials);
 }
 
 template <int NV>
-void launch_multiaxpy_n(size_t n, double *y, const VecSet &S, double *partials, int G, bool wide, hipStream_t s)
+void launch_multiaxpy_dot_n(size_t n, double *y, const VecSet &S, double *partials, int G, hipStream_t s)
 {
-    if (wide)
-        hipLaunchKernelGGL((k_multiaxpy<NV, 2>), dim3(G), dim3(256), 0, s, n, y, S, partials);
-    else
-        hipLaunchKernelGGL((k_multiaxpy<NV, 1>), dim3(G), dim3(256), 0, s, n, y, S, partials);
-}
-
-template <int NV>
-void launch_multiaxpy_dot_n(size_t n, double *y, const VecSet &S, double *partials, int G, bool wide,
-                            hipStream_t s)
-{
-    if (wide)
-        hipLaunchKernelGGL((k_multiaxpy_dot<NV, 2>), dim3(G), dim3(256), 0, s, n, y, S, partials);
-    else
-        hipLaunchKernelGGL((k_multiaxpy_dot<NV, 1>), dim3(G), dim3(256), 0, s, n, y, S, partials);
+    hipLaunchKernelGGL((k_multiaxpy_dot<NV>), dim3(G), dim3(256), 0, s, n, y, S, partials);
 }
 
 template <int NV>
 void launch_corr_n(size_t n, double *u, double *w, const CorrSet &S, double inv_rho, double hq, double *partials,
-                   int G, bool wide, hipStream_t s)
+                   int G, hipStream_t s)
 {
-    if (wide)
-        hipLaunchKernelGGL((k_corr_axpy_dot<NV, 2>), dim3(G), dim3(256), 0, s, n, u, w, S, inv_rho, hq, partials);
-    else
-        hipLaunchKernelGGL((k_corr_axpy_dot<NV, 1>), dim3(G), dim3(256), 0, s, n, u, w, S, inv_rho, hq, partials);
+    hipLaunchKernelGGL((k_corr_axpy_dot<NV>), dim3(G), dim3(256), 0, s, n, u, w, S, inv_rho, hq, partials);
 }
 
 // Calls f(std::integral_constant<int, NV>) for 1 <= nv <= kMultiMax.
@@ -501,9 +406,8 @@ hipError_t launch_multidot(size_t n, const double *w, const double *const *v, in
     if (nv < 1 || nv > kMultiMax) return hipErrorInvalidValue;
     VecSet S{};
     for (int i = 0; i < nv; ++i) S.v[i] = v[i];
-    const bool wide = vec_wide(n, S, nv, {w});
-    const int G = vec_grid(wide ? n / 2 : n);
-    dispatch_nv(nv, [&](auto NVc) { launch_multidot_n<decltype(NVc)::value>(n, w, S, partials, G, wide, s); });
+    const int G = vec_grid(n);
+    dispatch_nv(nv, [&](auto NVc) { launch_multidot_n<decltype(NVc)::value>(n, w, S, partials, G, s); });
     return launch_sum_partials(partials, G, nv, stage, out, s);
 }
 
@@ -516,11 +420,9 @@ hipError_t launch_multiaxpy(size_t n, double *y, const double *const *v, const d
         S.v[i] = v[i];
         S.a[i] = a[i];
     }
-    const bool wide = vec_wide(n, S, nv, {y});
-    const int G = vec_grid(wide ? n / 2 : n);
+    const int G = vec_grid(n);
     if (nblocks_out) *nblocks_out = G;
-    dispatch_nv(nv,
-                [&](auto NVc) { launch_multiaxpy_n<decltype(NVc)::value>(n, y, S, norm_partials, G, wide, s); });
+    dispatch_nv(nv, [&](auto NVc) { launch_multiaxpy_n<decltype(NVc)::value>(n, y, S, norm_partials, G, s); });
     return hipGetLastError();
 }
 
@@ -533,10 +435,8 @@ hipError_t launch_multiaxpy_dot(size_t n, double *y, const double *const *v, con
         S.v[i] = v[i];
         S.a[i] = a[i];
     }
-    const bool wide = vec_wide(n, S, nv, {y});
-    const int G = vec_grid(wide ? n / 2 : n);
-    dispatch_nv(nv,
-                [&](auto NVc) { launch_multiaxpy_dot_n<decltype(NVc)::value>(n, y, S, partials, G, wide, s); });
+    const int G = vec_grid(n);
+    dispatch_nv(nv, [&](auto NVc) { launch_multiaxpy_dot_n<decltype(NVc)::value>(n, y, S, partials, G, s); });
     return launch_sum_partials(partials, G, nv + 1, stage, out, s);
 }
 
@@ -552,12 +452,8 @@ hipError_t launch_corr_axpy_dot(size_t n, double *u, double *w, const double *co
         S.cw[i] = cw[i];
         S.sd[i] = sd[i];
     }
-    bool wide = vec_wide(n, {u, w});
-    for (int i = 0; i < nv; ++i) wide = wide && (uintptr_t)S.v[i] % 16 == 0;
-    const int G = vec_grid(wide ? n / 2 : n);
-    dispatch_nv(nv, [&](auto NVc) {
-        launch_corr_n<decltype(NVc)::value>(n, u, w, S, inv_rho, hq, partials, G, wide, s);
-    });
+    const int G = vec_grid(n);
+    dispatch_nv(nv, [&](auto NVc) { launch_corr_n<decltype(NVc)::value>(n, u, w, S, inv_rho, hq, partials, G, s); });
     return launch_sum_partials(partials, G, nv + 2, stage, out, s);
 }
 
