@@ -354,7 +354,10 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *h, const double *b_dev, doubl
  * The column block H1_z (all couplings inside a column: cell terms, the
  * self parts of the horizontal faces, the vertical faces) is banded with 5
  * sub- and 5 super-diagonals in the row order r = 6 k + a; it is factorised
- * without pivoting (SPD).  Smoother: u <- u + omega H1_z^{-1} (b - H1 u)
+ * without pivoting (SPD), in FP64.  A mixed hierarchy stores the factors in
+ * FP32 (half the bytes the sweeps stream; forward and back substitution still
+ * run in FP64), so its line solves and sweeps use the FP32-rounded factors.
+ * Smoother: u <- u + omega H1_z^{-1} (b - H1 u)
  * with the hierarchy's omega.  Transfers: P1 e0 adds e0 to u_0 and u_3 (the
  * bottom and top values of the constant mode); R1 = P1^T.  NLO V-cycle
  * from a zero guess: nu_pre DG1 sweeps, b0 = R1 (b - H1 u), one lowest-order
@@ -367,7 +370,8 @@ tpmg_status tpmg_mixed_solve(const tpmg_hierarchy *h, const double *b_dev, doubl
  * DG1 vectors must stay below 4 GiB (6 n^2 nz < 2^29) (TPMG_ERR_SHAPE).
  *
  * OWNERSHIP: the caller owns the DG1 workspace (tpmg_dg1_workspace_bytes,
- * 256-byte aligned: band factors of 88 n^2 nz doubles, nine DG1 vectors,
+ * 256-byte aligned: band factors of 66 n^2 nz values (doubles; floats in a
+ * mixed hierarchy), nine DG1 vectors,
  * two lowest-order vectors); the handle aliases it and h.  Calls use the
  * reduction buffers and coarse-level vectors of h: they must not overlap
  * other calls on h.  Buffers of one call must not alias unless stated.
@@ -399,7 +403,9 @@ tpmg_status tpmg_dg1_vcycle(const tpmg_dg1 *g, const double *b_dev, double *z_de
 tpmg_status tpmg_dg1_solve(const tpmg_dg1 *g, const double *b_dev, double *x_dev, const tpmg_solve_opts *opts,
                            tpmg_solve_info *info, void *stream);
 /* Copy of the band factors, [col = j n + i][r][e] (n^2 x 6 nz x 11): L(r, r-5+e)
- * for e < 5, U(r, r) for e = 5, U(r, r+e-5) for e > 5 (0 outside the matrix). */
+ * for e < 5, U(r, r) for e = 5, U(r, r+e-5) for e > 5 (0 outside the matrix).
+ * In a mixed hierarchy: the stored FP32 values, with U(r, r) given as the
+ * reciprocal of the stored FP32 value of 1 / U(r, r). */
 tpmg_status tpmg_dg1_factors(const tpmg_dg1 *g, double *f_dev, void *stream);
 /* Release the handle (not the workspace).  NULL is accepted. */
 tpmg_status tpmg_dg1_destroy(tpmg_dg1 *g);

@@ -60,11 +60,14 @@ struct Dg1Lane {
     unsigned oc, ocw, ocs;       // byte offset of level 0 in a face array: own, west, south column
     unsigned row;                // bytes between storage rows (W values)
     unsigned of;                 // byte offset of this lane within a factor row
+    unsigned frow;               // bytes between factor rows (W factor values)
     Rsrc rE, rN, rU, rF;         // faces E, N, U; this tile's band factors
 };
 
-// cb: the workgroup's block of 256 consecutive columns.
-__device__ __forceinline__ Dg1Lane dg1_lane(const Dg1Level &G, const double *fac, int cb)
+// cb: the workgroup's block of 256 consecutive columns; FT: the type the
+// band factors are stored in.
+template <typename FT = double>
+__device__ __forceinline__ Dg1Lane dg1_lane(const Dg1Level &G, const FT *fac, int cb)
 {
     Dg1Lane q;
     const int plane = G.plane, nz = G.nz, W = tile_width(plane);
@@ -84,13 +87,14 @@ __device__ __forceinline__ Dg1Lane dg1_lane(const Dg1Level &G, const double *fac
     q.row = (unsigned)W * 8u;
     // a wavefront is one tile (W = 64) or lies in the single tile (W = plane)
     const unsigned tile = __builtin_amdgcn_readfirstlane((unsigned)(col / W));
-    q.of = (unsigned)(col - (int)tile * W) * 8u;
+    q.of = (unsigned)(col - (int)tile * W) * (unsigned)sizeof(FT);
+    q.frow = (unsigned)W * (unsigned)sizeof(FT);
     const size_t fstride = (size_t)nz * plane;
     q.rE = make_rsrc(G.c, fstride * 8);
     q.rN = make_rsrc(G.c + fstride, fstride * 8);
     q.rU = make_rsrc(G.c + 2 * fstride, fstride * 8);
     const size_t tile_vals = (size_t)rows * kNf * W;
-    q.rF = make_rsrc(fac ? fac + tile * tile_vals : G.c, fac ? tile_vals * 8 : 0);
+    q.rF = fac ? make_rsrc(fac + tile * tile_vals, tile_vals * sizeof(FT)) : make_rsrc(G.c, 0);
     return q;
 }
 
@@ -252,9 +256,10 @@ __device__ __forceinline__ void ld6(double (&v)[6], Rsrc r, unsigned voff, unsig
 // elimination restricted to the band).  No pivoting: H1_z is symmetric
 // positive definite.  A non-positive or non-finite pivot counts into *bad.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dg1_factor(Dg1Level G, double *__restrict__ fac, int *__restrict__ bad)
+template <typename FT>
+__global__ __launch_bounds__(256) void k_dg1_factor(Dg1Level G, FT *__restrict__ fac, int *__restrict__ bad)
 {
-    const Dg1Lane q = dg1_lane(G, fac, xcd_remap(blockIdx.x, gridDim.x));
+    const Dg1Lane q = dg1_lane<FT>(G, fac, xcd_remap(blockIdx.x, gridDim.x));
     const int nz = G.nz;
     const unsigned oo = q.active ? q.of : 0xFFFFFFFFu;
     double Uw[5][6], Iw[5];  // rows r-1 .. r-5: U(q, q..q+5), 1/U(q, q)
@@ -311,10 +316,10 @@ __global__ __launch_bounds__(256) void k_dg1_factor(Dg1Level G, double *__restri
             for (int j = 0; j < 6; ++j) Uw[0][j] = u[j];
             const unsigned rr = (unsigned)(kNb * k + a) * kNf;
 #pragma unroll
-            for (int e = 0; e < 5; ++e) bstore(l[5 - e], q.rF, oo, (rr + e) * q.row);
-            bstore(iu, q.rF, oo, (rr + 5) * q.row);
+            for (int e = 0; e < 5; ++e) bstore((FT)l[5 - e], q.rF, oo, (rr + e) * q.frow);
+            bstore((FT)iu, q.rF, oo, (rr + 5) * q.frow);
 #pragma unroll
-            for (int j = 1; j < 6; ++j) bstore(u[j], q.rF, oo, (rr + 5 + j) * q.row);
+            for (int j = 1; j < 6; ++j) bstore((FT)u[j], q.rF, oo, (rr + 5 + j) * q.frow);
         }
     }
     if (q.active && nbad) atomicAdd(bad, nbad);
@@ -348,12 +353,12 @@ struct Dg1Bwd {
 // CP: cache policy of the data the sweep reads or writes once (the band
 // factors, b, the final output); y, written in the forward pass and read back
 // in the backward pass, and u keep the default policy.
-template <int MODE, bool PF, int CP>
-__global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__restrict__ fac,
+template <int MODE, bool PF, int CP, typename FT>
+__global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const FT *__restrict__ fac,
                                                    const double *__restrict__ u, const double *__restrict__ b,
                                                    double *__restrict__ out, double omega)
 {
-    const Dg1Lane q = dg1_lane(G, fac, xcd_remap(blockIdx.x, gridDim.x));
+    const Dg1Lane q = dg1_lane<FT>(G, fac, xcd_remap(blockIdx.x, gridDim.x));
     const unsigned nz = (unsigned)G.nz;
     const size_t vbytes = (size_t)kNb * nz * G.plane * 8;
     const Rsrc ru = make_rsrc(u ? u : b, vbytes), rb = make_rsrc(b, vbytes), ro = make_rsrc(out, vbytes);
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__r
         for (int a = 0; a < kNb; ++a)
 #pragma unroll
             for (int e = 0; e < 5; ++e)
-                F.l[a][e] = bload<CP>(double(), q.rF, q.of, ((kNb * k + a) * kNf + e) * q.row);
+                F.l[a][e] = (double)bload<CP>(FT(), q.rF, q.of, ((kNb * k + a) * kNf + e) * q.frow);
     };
     auto load_bwd = [&](Dg1Bwd &B, unsigned k) {
         ld6(B.y, ro, q.ov, k, nz, q.row);
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(256) void k_dg1_sweep(Dg1Level G, const double *__r
         for (int a = 0; a < kNb; ++a)
 #pragma unroll
             for (int e = 0; e < 6; ++e)
-                B.u[a][e] = bload<CP>(double(), q.rF, q.of, ((kNb * k + a) * kNf + 5 + e) * q.row);
+                B.u[a][e] = (double)bload<CP>(FT(), q.rF, q.of, ((kNb * k + a) * kNf + 5 + e) * q.frow);
     };
 
     double yw[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // y(r-1) .. y(r-5)
@@ -494,7 +499,7 @@ __global__ __launch_bounds__(256) void k_dg1_op(Dg1Level G, int kc, const double
     int cb;
     unsigned k0, k1;
     dg1_chunk(G, kc, cb, k0, k1);
-    const Dg1Lane q = dg1_lane(G, nullptr, cb);
+    const Dg1Lane q = dg1_lane<double>(G, nullptr, cb);
     const unsigned nz = (unsigned)G.nz;
     const size_t vbytes = (size_t)kNb * nz * G.plane * 8;
     const Rsrc rx = make_rsrc(x, vbytes), rx2 = make_rsrc(x2 ? x2 : x, vbytes);
@@ -584,7 +589,7 @@ __global__ __launch_bounds__(256) void k_dg1_resid_restrict(Dg1Level G, int kc, 
     int cb;
     unsigned k0, k1;
     dg1_chunk(G, kc, cb, k0, k1);
-    const Dg1Lane q = dg1_lane(G, nullptr, cb);
+    const Dg1Lane q = dg1_lane<double>(G, nullptr, cb);
     const unsigned nz = (unsigned)G.nz;
     const size_t vbytes = (size_t)kNb * nz * G.plane * 8;
     const Rsrc ru = make_rsrc(u, vbytes), rb = make_rsrc(b, vbytes);
@@ -653,7 +658,8 @@ __global__ __launch_bounds__(256) void k_dg1_prolong(int plane, int nz, const T 
 }
 
 // Band factors in the order [col][row][entry] with U(r, r) itself in entry 5.
-__global__ __launch_bounds__(256) void k_dg1_factors_out(int plane, int nz, const double *__restrict__ fac,
+template <typename FT>
+__global__ __launch_bounds__(256) void k_dg1_factors_out(int plane, int nz, const FT *__restrict__ fac,
                                                          double *__restrict__ dst)
 {
     const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -663,7 +669,7 @@ __global__ __launch_bounds__(256) void k_dg1_factors_out(int plane, int nz, cons
     const size_t r = rem / kNf, e = rem - r * kNf;
     const int W = tile_width(plane);
     const size_t tile = col / W, lane = col - tile * W;
-    const double v = fac[tile * rows * kNf * W + (r * kNf + e) * W + lane];
+    const double v = (double)fac[tile * rows * kNf * W + (r * kNf + e) * W + lane];
     dst[g] = (e == 5) ? 1.0 / v : v;
 }
 
@@ -687,26 +693,40 @@ inline unsigned dg1_chunk_blocks(const Dg1Level &G, int kc)
 
 // ---- launchers ------------------------------------------------------------------
 
-hipError_t launch_dg1_factor(const Dg1Level &G, double *fac, int *bad, hipStream_t s)
+hipError_t launch_dg1_factor(const Dg1Level &G, void *fac, int *bad, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dg1_factor, dim3(dg1_blocks(G.plane)), dim3(256), 0, s, G, fac, bad);
+    if (G.fac32)
+        hipLaunchKernelGGL(k_dg1_factor<float>, dim3(dg1_blocks(G.plane)), dim3(256), 0, s, G, (float *)fac, bad);
+    else
+        hipLaunchKernelGGL(k_dg1_factor<double>, dim3(dg1_blocks(G.plane)), dim3(256), 0, s, G, (double *)fac,
+                           bad);
     return hipGetLastError();
 }
 
-template <bool PF, int CP>
-void dg1_sweep_pf(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b, double *out,
+template <bool PF, int CP, typename FT>
+void dg1_sweep_ft(const Dg1Level &G, const FT *fac, int mode, const double *u, const double *b, double *out,
                   double omega, hipStream_t s)
 {
     const dim3 grid(dg1_blocks(G.plane)), block(256);
     if (mode == DG1_SWEEP_GENERAL)
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_GENERAL, PF, CP>), grid, block, 0, s, G, fac, u, b, out, omega);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_GENERAL, PF, CP, FT>), grid, block, 0, s, G, fac, u, b, out, omega);
     else if (mode == DG1_SWEEP_ZERO)
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_ZERO, PF, CP>), grid, block, 0, s, G, fac, nullptr, b, out, omega);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_ZERO, PF, CP, FT>), grid, block, 0, s, G, fac, nullptr, b, out, omega);
     else
-        hipLaunchKernelGGL((k_dg1_sweep<DG1_SOLVE, PF, CP>), grid, block, 0, s, G, fac, nullptr, b, out, 1.0);
+        hipLaunchKernelGGL((k_dg1_sweep<DG1_SOLVE, PF, CP, FT>), grid, block, 0, s, G, fac, nullptr, b, out, 1.0);
 }
 
-hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b,
+template <bool PF, int CP>
+void dg1_sweep_pf(const Dg1Level &G, const void *fac, int mode, const double *u, const double *b, double *out,
+                  double omega, hipStream_t s)
+{
+    if (G.fac32)
+        dg1_sweep_ft<PF, CP>(G, (const float *)fac, mode, u, b, out, omega, s);
+    else
+        dg1_sweep_ft<PF, CP>(G, (const double *)fac, mode, u, b, out, omega, s);
+}
+
+hipError_t launch_dg1_sweep(const Dg1Level &G, const void *fac, int mode, const double *u, const double *b,
                             double *out, double omega, hipStream_t s)
 {
     // TPMG_DG1_PF = 1: the next cell's forward / backward loads issued ahead
@@ -717,7 +737,7 @@ hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, cons
     // last-level cache (TPMG_DG1_NT=0: never, 1: always): measured at
     // 256^2 x 64 (2.2 GB of factors), general sweep 0.646 vs 0.715 ms.
     static const int nt = env_int("TPMG_DG1_NT");
-    const bool big = (size_t)G.plane * kNb * G.nz * kNf * 8 >= ((size_t)1 << 28);
+    const bool big = (size_t)G.plane * kNb * G.nz * kNf * (G.fac32 ? 4 : 8) >= ((size_t)1 << 28);
     if (pf == 1)
         dg1_sweep_pf<true, 0>(G, fac, mode, u, b, out, omega, s);
     else if (nt == 1 || (nt != 0 && big))
@@ -782,11 +802,15 @@ hipError_t launch_dg1_prolong(const Dg1Level &G, const void *e0, int fp32, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_dg1_factors_out(const Dg1Level &G, const double *fac, double *dst, hipStream_t s)
+hipError_t launch_dg1_factors_out(const Dg1Level &G, const void *fac, double *dst, hipStream_t s)
 {
     const size_t total = (size_t)G.plane * kNb * G.nz * kNf;
-    hipLaunchKernelGGL(k_dg1_factors_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G.plane, G.nz, fac,
-                       dst);
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (G.fac32)
+        hipLaunchKernelGGL(k_dg1_factors_out<float>, grid, dim3(256), 0, s, G.plane, G.nz, (const float *)fac, dst);
+    else
+        hipLaunchKernelGGL(k_dg1_factors_out<double>, grid, dim3(256), 0, s, G.plane, G.nz, (const double *)fac,
+                           dst);
     return hipGetLastError();
 }
 

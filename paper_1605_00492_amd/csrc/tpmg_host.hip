@@ -1492,7 +1492,8 @@ struct tpmg_dg1 {
     tpmg_hierarchy *h = nullptr;
     Dg1Level G{};
     size_t nv = 0;                     // 6 n^2 nz unknowns
-    double *fac = nullptr, *tab = nullptr;
+    void *fac = nullptr;   // band factors: FP32 for a mixed hierarchy, else FP64
+    double *tab = nullptr;
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     double *A = nullptr, *B = nullptr;  // sweep vectors of the V-cycle and the component calls
     double *b0 = nullptr, *e0 = nullptr;  // lowest-order level-0 vectors (FP64 correction)
@@ -1514,7 +1515,9 @@ size_t plan_dg1(const tpmg_hierarchy *h, tpmg_dg1 *g, char *base)
     };
     const size_t plane = (size_t)h->l64[0].plane, nz = (size_t)h->nz;
     const size_t nv = plane * 6 * nz, ncell = plane * nz;
-    double *fac = take(nv * kDg1Nf * 8);
+    // a mixed hierarchy keeps the band factors in FP32 (the NLO smoother of
+    // the FP32 V-cycle path; arithmetic stays FP64), half the bytes
+    void *fac = take(nv * kDg1Nf * (h->mixed ? 4 : 8));
     double *tab = take(5 * nz * 8);
     double *v[9];
     for (int i = 0; i < 9; ++i) v[i] = take(nv * 8);
@@ -1646,6 +1649,7 @@ tpmg_status tpmg_dg1_setup(const tpmg_hierarchy *hc, void *workspace_dev, size_t
     g->G.plane = h->l64[0].plane;
     g->G.c = (const double *)h->l64[0].c;
     g->G.tab = g->tab;
+    g->G.fac32 = h->mixed ? 1 : 0;
     // per-k scalars of the finest level: s_k, a_h s_k, 4 a_h s_k, 4 a_z / s_k, a_z / t_{k+1/2}
     std::vector<double> sk(nz, 1.0), tk(nz, 1.0), tab(5 * (size_t)nz, 0.0);
     {

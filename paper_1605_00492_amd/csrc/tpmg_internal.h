@@ -184,6 +184,7 @@ struct Dg1Level {
     int n, nz, plane;
     const double *c;    // level-0 faces [3][nz * plane] (tiled storage, nz rows)
     const double *tab;  // [5][nz]: s_k, a_h s_k, 4 a_h s_k, 4 a_z / s_k, a_z / t_{k+1/2} (0 at the top)
+    int fac32;          // band factors stored in FP32 (computed in FP64, used in FP64 arithmetic)
 };
 enum Dg1Sweep : int {
     DG1_SWEEP_ZERO = 0,     // out = omega H1_z^{-1} b
@@ -192,8 +193,8 @@ enum Dg1Sweep : int {
 };
 // Band LU of every column block into fac (6 nz rows x 11 entries per column,
 // tiled by 64 columns); non-positive pivots are counted into *bad.
-hipError_t launch_dg1_factor(const Dg1Level &G, double *fac, int *bad, hipStream_t s);
-hipError_t launch_dg1_sweep(const Dg1Level &G, const double *fac, int mode, const double *u, const double *b,
+hipError_t launch_dg1_factor(const Dg1Level &G, void *fac, int *bad, hipStream_t s);
+hipError_t launch_dg1_sweep(const Dg1Level &G, const void *fac, int mode, const double *u, const double *b,
                             double *out, double omega, hipStream_t s);
 hipError_t launch_dg1_apply(const Dg1Level &G, const double *x, double *y, hipStream_t s);
 // r = b - H1 x (r may be null) and partial sums of (r, r)
@@ -208,7 +209,7 @@ hipError_t launch_dg1_resid_restrict(const Dg1Level &G, const double *u, const d
 // u += P1 e0 (e0 a lowest-order level-0 vector, float when fp32)
 hipError_t launch_dg1_prolong(const Dg1Level &G, const void *e0, int fp32, double *u, hipStream_t s);
 // factors as [col][row][entry] with U(r, r) in entry 5
-hipError_t launch_dg1_factors_out(const Dg1Level &G, const double *fac, double *dst, hipStream_t s);
+hipError_t launch_dg1_factors_out(const Dg1Level &G, const void *fac, double *dst, hipStream_t s);
 
 // Sweep chunking for a precision, sweep mode and column height: M cells per chunk, CPW
 // chunks per wavefront, P wavefronts per 64-column tile; false if nz is not

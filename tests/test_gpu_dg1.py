@@ -121,6 +121,85 @@ def test_fp64_solve_matches_oracle_iterate(case):
     assert info["true_rel_residual"] <= 1.05e-8
 
 
+def _stored_fp32(ref):
+    """The oracle's band factors as a mixed hierarchy stores them: every entry
+    rounded to FP32, the diagonal entry as the FP32 value of 1 / U(r, r)."""
+    f = ref.astype(np.float32).astype(np.float64)
+    with np.errstate(divide="ignore"):
+        f[..., 5] = (1.0 / ref[..., 5]).astype(np.float32).astype(np.float64)
+    return f
+
+
+def _band_solve(F, r, n, nz):
+    """x = (L U)^{-1} r column by column with stored factors F ([j, i, row,
+    entry], entry 5 the reciprocal of U(row, row)): forward and back
+    substitution in FP64, r and x in the (6, nz, n, n) layout."""
+    m = 6 * nz
+    rc = oracle.dg1_to_columns(r).reshape(n, n, m)
+    y = np.zeros_like(rc)
+    for row in range(m):
+        acc = rc[..., row].copy()
+        for d in range(1, 6):
+            if row - d >= 0:
+                acc -= F[..., row, 5 - d] * y[..., row - d]
+        y[..., row] = acc
+    x = np.zeros_like(rc)
+    for row in range(m - 1, -1, -1):
+        acc = y[..., row].copy()
+        for d in range(1, 6):
+            if row + d < m:
+                acc -= F[..., row, 5 + d] * x[..., row + d]
+        x[..., row] = acc * F[..., row, 5]
+    return oracle.dg1_from_columns(x.reshape(-1), n, nz)
+
+
+def test_mixed_factors_are_fp32_roundings(case):
+    """A mixed hierarchy stores the FP64 factors rounded to FP32: equal to the
+    oracle's factors rounded the same way (both FP64 factorisations agree to
+    1e-13, so at most a value sitting on a rounding boundary could differ, by
+    one FP32 unit in the last place)."""
+    got = host(case["D"]["mixed"].factors())
+    stored = _stored_fp32(case["G"].factors())
+    expect = stored.copy()
+    nz_ = stored[..., 5] != 0
+    expect[..., 5][nz_] = 1.0 / stored[..., 5][nz_]
+    scale = np.maximum(np.abs(expect), np.finfo(np.float64).tiny)
+    err = np.abs(got - expect) / scale
+    exact = np.count_nonzero(got == expect)
+    print(f"[gpu] {case['name']} mixed factors: {exact} of {got.size} equal, max rel diff {err.max():.2e}",
+          flush=True)
+    assert err.max() <= 2.0 ** -23, err.max()
+
+
+def test_mixed_line_solve_and_sweeps_use_the_fp32_factors(case):
+    """The mixed level's line solve and sweeps are the FP64 substitutions
+    with the FP32-rounded factors (emulated here from the oracle's factors and
+    operator); against the FP64 oracle they differ by the factor rounding."""
+    n, nz = case["n"], case["nz"]
+    ref = case["G"].factors()
+    F = _stored_fp32(ref)
+    D, G = case["D"]["mixed"], case["G"]
+    omega = 0.8
+    r, u, b = _rand(case), _rand(case), _rand(case)
+    # the emulation itself: with the FP64 factors it is the oracle's line solve
+    F64 = ref.copy()
+    nzd = ref[..., 5] != 0
+    F64[..., 5][nzd] = 1.0 / ref[..., 5][nzd]
+    assert rel_err(_band_solve(F64, r, n, nz), G.line_solve(r)) <= 1e-12
+    got = host(D.line_solve(to_dev(r)))
+    emu = _band_solve(F, r, n, nz)
+    err, err64 = rel_err(got, emu), rel_err(got, G.line_solve(r))
+    print(f"[gpu] {case['name']} mixed line solve: {err:.2e} vs FP32-factor emulation, "
+          f"{err64:.2e} vs FP64 factors", flush=True)
+    assert err <= 1e-10, err
+    got0 = host(D.smooth(to_dev(b), None))
+    err0 = rel_err(got0, omega * _band_solve(F, b, n, nz))
+    got1 = host(D.smooth(to_dev(b), to_dev(u)))
+    err1 = rel_err(got1, u + omega * _band_solve(F, b - G.apply(u), n, nz))
+    print(f"[gpu] {case['name']} mixed sweeps: zero {err0:.2e}, general {err1:.2e}", flush=True)
+    assert err0 <= 1e-10 and err1 <= 1e-10, (err0, err1)
+
+
 def test_mixed_solve_matches_oracle(case):
     """FP32 lowest-order V-cycle inside the FP64 DG1 sweeps and CG
     (flexible beta): the solution to 1e-8 against the oracle's FP64 one."""
