@@ -1395,11 +1395,14 @@ template <typename T, int M, int CPW, int LB>
 hipError_t sweep_m(const Level<T> &L, int mode, const T *u, const T *b, T *out, const T *ec, T omega, int P,
                    hipStream_t s)
 {
-    // Measured on 1024^2 x 128: FP32 (two workgroups per CU) is fastest in
-    // plain row order, FP64 (one per CU) with blocks of 2 tiles x 32 rows.
+    // Tile order: plain row order in both precisions (measured on 1024^2 x
+    // 128 with the non-temporal hints and the lane exchange: FP64 V-cycle
+    // 9.58 vs 9.96 ms for blocks of 2 tiles x 32 rows, 9.87 ms for 4 x 16;
+    // FP32 V-cycle 4.24 vs 4.27-4.59 ms for 1 x 4 to 4 x 2 and 2 x 16).
+    // TPMG_SWEEP_BI / TPMG_SWEEP_BJ select blocks of BI tiles x BJ rows.
     static const int ebi = env_int("TPMG_SWEEP_BI"), ebj = env_int("TPMG_SWEEP_BJ");
-    const int tbi = ebi >= 0 ? ebi : (sizeof(T) == 8 ? 2 : 0);
-    const int tbj = ebj > 0 ? ebj : (sizeof(T) == 8 ? 32 : 1);
+    const int tbi = ebi >= 0 ? ebi : 0;
+    const int tbj = ebj > 0 ? ebj : 1;
     const int tiles = (L.plane + 63) / 64;
     const dim3 block(64 * P);
     const size_t lds = (size_t)P * CPW * 512 * sizeof(T);
