@@ -22,6 +22,34 @@ thread_local std::string g_last_error;
 
 constexpr size_t kAlign = 256;
 
+// Pinned host blocks for the scalars a solve reads back (Scalars followed by
+// kMultiMax + 2 doubles), kept for reuse by later hierarchies: pinning host
+// memory costs more than the rest of the host side of a set-up.
+constexpr size_t kPinnedBytes = sizeof(Scalars) + (kMultiMax + 2) * sizeof(double);
+std::mutex g_pinned_mu;
+std::vector<void *> g_pinned_free;
+
+void *pinned_take()
+{
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            void *p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    return hipHostMalloc(&p, kPinnedBytes, hipHostMallocDefault) == hipSuccess ? p : nullptr;
+}
+
+void pinned_give(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_pinned_free.push_back(p);
+}
+
 struct LevelBufs {
     int n = 0, plane = 0;
     void *c = nullptr;                       // [3][nz * plane], tiled storage
@@ -55,6 +83,7 @@ struct tpmg_hierarchy {
     double *partials = nullptr;
     Scalars *sc = nullptr;
     int *bad = nullptr;
+    void *scal[2] = {nullptr, nullptr};  // per-level scalars mu, wh, wz of all levels: FP64, FP32
     Scalars *sc_host = nullptr;  // pinned, followed by kMultiMax + 2 doubles (dots_host)
     double *dots_host = nullptr;
     char *ws = nullptr;
@@ -146,6 +175,9 @@ size_t plan_workspace(const tpmg_desc &d, tpmg_hierarchy *h)
     const size_t nz = (size_t)d.nz;
     for (int pass = 0; pass < (mixed ? 2 : 1); ++pass) {
         const size_t S = pass == 0 ? sizeof(double) : sizeof(float);
+        // mu, wh, wz of every level in one block, uploaded by one copy
+        char *scal = (char *)take((size_t)d.nlevels * 3 * nz * S);
+        if (h) h->scal[pass] = scal;
         for (int l = 0; l < d.nlevels; ++l) {
             const int n = d.n >> l;
             const size_t cells = (size_t)n * n * nz;
@@ -154,9 +186,11 @@ size_t plan_workspace(const tpmg_desc &d, tpmg_hierarchy *h)
             B.n = n;
             B.plane = n * n;
             B.c = take(3 * cells * S);
-            B.mu = take(nz * S);
-            B.wh = take(nz * S);
-            B.wz = take(nz * S);
+            if (h) {
+                B.mu = scal + (size_t)(3 * l + 0) * nz * S;
+                B.wh = scal + (size_t)(3 * l + 1) * nz * S;
+                B.wz = scal + (size_t)(3 * l + 2) * nz * S;
+            }
             B.A = take(cells * S);
             B.B = take(cells * S);
             if (l > 0) {
@@ -633,13 +667,13 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
 
     auto bail = [&](tpmg_status code) {
         g_last_error = h->err;
-        if (h->sc_host) (void)hipHostFree(h->sc_host);
+        (void)hipStreamSynchronize(s);  // copies from host buffers of this call may be in flight
+        pinned_give(h->sc_host);
         delete h;
         return code;
     };
-    if (hipHostMalloc((void **)&h->sc_host, sizeof(Scalars) + (kMultiMax + 2) * sizeof(double), hipHostMallocDefault) !=
-        hipSuccess)
-        return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
+    h->sc_host = (Scalars *)pinned_take();
+    if (!h->sc_host) return bail(fail(h, TPMG_ERR_DEVICE, "hipHostMalloc failed"));
     h->dots_host = reinterpret_cast<double *>(reinterpret_cast<char *>(h->sc_host) + sizeof(Scalars));
 
     // per-level scalars: s_k, t_{k+1/2}
@@ -653,6 +687,10 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
         for (int k = 0; k + 1 < nz; ++k) tk[k] = 0.5 * (sk[k] + sk[k + 1]);
     }
     std::vector<std::vector<double>> mu(h->L), wh(h->L), wz(h->L);
+    // the blocks uploaded to h->scal (level l: mu, wh, wz), alive until the
+    // synchronisation below
+    std::vector<double> s64((size_t)h->L * 3 * nz);
+    std::vector<float> s32(h->mixed ? s64.size() : 0);
     for (int l = 0; l < h->L; ++l) {
         const double f = std::ldexp(1.0, 2 * l);
         mu[l].resize(nz);
@@ -662,27 +700,17 @@ tpmg_status tpmg_setup_hierarchy(const tpmg_desc *desc, const double *c_dev, int
             mu[l][k] = f * sk[k];
             wh[l][k] = desc->a_h * sk[k];
             wz[l][k] = (k + 1 < nz) ? f * desc->a_z / tk[k] : 0.0;
-        }
-        hipError_t e;
-        if ((e = hipMemcpyAsync(h->l64[l].mu, mu[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(h->l64[l].wh, wh[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(h->l64[l].wz, wz[l].data(), nz * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
-            return bail(hip_fail(h, e, "copy level scalars"));
-        if (h->mixed) {
-            std::vector<float> m32(nz), h32(nz), z32(nz);
-            for (int k = 0; k < nz; ++k) {
-                m32[k] = (float)mu[l][k];
-                h32[k] = (float)wh[l][k];
-                z32[k] = (float)wz[l][k];
-            }
-            if ((e = hipMemcpyAsync(h->l32[l].mu, m32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (e = hipMemcpyAsync(h->l32[l].wh, h32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (e = hipMemcpyAsync(h->l32[l].wz, z32.data(), nz * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (e = hipStreamSynchronize(s)) != hipSuccess)
-                return bail(hip_fail(h, e, "copy level scalars (fp32)"));
+            const size_t o = (size_t)3 * l * nz + k;
+            s64[o] = mu[l][k];
+            s64[o + nz] = wh[l][k];
+            s64[o + 2 * nz] = wz[l][k];
         }
     }
+    for (size_t i = 0; i < s32.size(); ++i) s32[i] = (float)s64[i];
     hipError_t e;
+    if ((e = hipMemcpyAsync(h->scal[0], s64.data(), s64.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (h->mixed && (e = hipMemcpyAsync(h->scal[1], s32.data(), s32.size() * 4, hipMemcpyHostToDevice, s)) != hipSuccess))
+        return bail(hip_fail(h, e, "copy level scalars"));
     const int plane0 = desc->n * desc->n;
     if ((e = launch_fill((double *)h->bad, 0.0, 1, s)) != hipSuccess ||
         (e = launch_copy_coeffs(c_dev, layout, (double *)h->l64[0].c, h->mixed ? (float *)h->l32[0].c : nullptr,
@@ -1455,7 +1483,7 @@ tpmg_status tpmg_destroy(tpmg_hierarchy *h)
         for (hipEvent_t e : h->pools[c].start) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->pools[c].stop) (void)hipEventDestroy(e);
     }
-    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    pinned_give(h->sc_host);
     delete h;
     return TPMG_OK;
 }
