@@ -266,7 +266,9 @@ tpmg_status tpmg_profile_read_level(tpmg_hierarchy *h, int32_t level, double *to
  */
 tpmg_status tpmg_bandwidth_probe(void *dst_dev, const void *src_dev, size_t bytes, void *stream);
 
-/* Release the handle (not the workspace).  NULL is accepted. */
+/* Release the handle (not the workspace).  NULL is accepted.  The small pinned
+ * host block a hierarchy reads its CG scalars into (a few hundred bytes) stays
+ * with the library and is reused by the next tpmg_setup_hierarchy. */
 tpmg_status tpmg_destroy(tpmg_hierarchy *h);
 
 /*
@@ -407,7 +409,9 @@ tpmg_status tpmg_dg1_solve(const tpmg_dg1 *g, const double *b_dev, double *x_dev
  * In a mixed hierarchy: the stored FP32 values, with U(r, r) given as the
  * reciprocal of the stored FP32 value of 1 / U(r, r). */
 tpmg_status tpmg_dg1_factors(const tpmg_dg1 *g, double *f_dev, void *stream);
-/* Release the handle (not the workspace).  NULL is accepted. */
+/* Release the handle (not the workspace).  NULL is accepted.  The small pinned
+ * host block a hierarchy reads its CG scalars into (a few hundred bytes) stays
+ * with the library and is reused by the next tpmg_setup_hierarchy. */
 tpmg_status tpmg_dg1_destroy(tpmg_dg1 *g);
 
 const char *tpmg_status_string(tpmg_status s);
