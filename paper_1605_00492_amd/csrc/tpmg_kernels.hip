@@ -940,7 +940,14 @@ __global__ __launch_bounds__(256) void k_solve_start(const double *__restrict__ 
 // XL (rows of whole tiles): p_new at the east / west neighbours comes from
 // the neighbouring lanes, formed there by the same expression (one pair of
 // loads at the tile edges instead of two pairs per cell).
-template <int KC, typename ZT, int CP, bool XL>
+// RW = 4 (with XL): the workgroup's four wavefronts take the same tile in
+// four consecutive rows; p_new and c_N of a level go through LDS, so the
+// inner rows take their north / south p_new and the south face from the
+// neighbouring wavefront instead of loading z, p_old and c_N there (only the
+// outer rows of the four load them).  1024^2 x 128: 1.343 vs 1.383 ms (8 rows
+// per workgroup: 1.368 ms).  The (p, q) partial sums then group other
+// columns per workgroup.
+template <int KC, typename ZT, int CP, bool XL, int RW = 0>
 __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, const ZT *__restrict__ zt,
                                                               const double *__restrict__ p_old,
                                                               double *__restrict__ p_new,
@@ -950,7 +957,19 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
 {
     int col, k0;
     bool active;
-    stream_coords<KC>(L, col, k0, active);
+    constexpr bool R4 = RW != 0;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if constexpr (R4) {
+        // blocks: (k-chunk, group of RW rows, tile column), row groups outer
+        const int TR = L.n >> 6, per_kc = (L.n / RW) * TR;
+        const int blk = xcd_remap(blockIdx.x, gridDim.x);
+        const int kc = blk / per_kc, r = blk % per_kc;
+        col = (RW * (r / TR) + wv) * L.n + (r % TR) * 64 + (int)(threadIdx.x & 63);
+        k0 = kc * KC;
+        active = true;
+    } else {
+        stream_coords<KC>(L, col, k0, active);
+    }
     const int nz = L.nz;
     const StencilRows<double> R(L, col);
     const size_t n = (size_t)nz * L.plane;
@@ -991,14 +1010,23 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             w.pE = PL(k, R.oe);
             w.pW = PL(k, R.ow);
         }
-        w.zN = ZL(k, R.on);
-        w.zS = ZL(k, R.os);
-        w.pN = PL(k, R.on);
-        w.pS = PL(k, R.os);
+        w.zN = ZT(0);
+        w.zS = ZT(0);
+        w.pN = 0.0;
+        w.pS = 0.0;
+        w.cNs = 0.0;
+        if (!R4 || wv == RW - 1) {
+            w.zN = ZL(k, R.on);
+            w.pN = PL(k, R.on);
+        }
+        if (!R4 || wv == 0) {
+            w.zS = ZL(k, R.os);
+            w.pS = PL(k, R.os);
+            w.cNs = bload(double(), R.rN, R.os, sk);
+        }
         w.cE = bload(double(), R.rE, R.oc, sk);
         w.cEw = bload(double(), R.rE, R.ow, sk);
         w.cN = bload(double(), R.rN, R.oc, sk);
-        w.cNs = bload(double(), R.rN, R.os, sk);
         w.cU = bload<CP>(double(), R.rU, R.oc, sk);
         w.zu = ZT(0);
         w.pu = 0.0;
@@ -1036,11 +1064,29 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
                 pE = comb(cur.zE, cur.pE);
                 pW = comb(cur.zW, cur.pW);
             }
+            double pN, pS, cNs;
+            if constexpr (R4) {
+                // double-buffered by level: a wavefront writes slot t & 1 of
+                // level k + 1 only after the barrier of level k, which every
+                // wavefront reaches after reading that slot for level k - 1
+                __shared__ double xp[2][R4 ? RW : 1][64], xc[2][R4 ? RW : 1][64];
+                const int sl = t & 1;
+                xp[sl][wv][lane] = pc;
+                xc[sl][wv][lane] = cur.cN;
+                __syncthreads();
+                pN = wv == RW - 1 ? comb(cur.zN, cur.pN) : xp[sl][wv + 1][lane];
+                pS = wv == 0 ? comb(cur.zS, cur.pS) : xp[sl][wv - 1][lane];
+                cNs = wv == 0 ? cur.cNs : xc[sl][wv - 1][lane];
+            } else {
+                pN = comb(cur.zN, cur.pN);
+                pS = comb(cur.zS, cur.pS);
+                cNs = cur.cNs;
+            }
             double qq = L.mu[k] * pc;
             qq = __builtin_fma(h * cur.cE, pc - pE, qq);
             qq = __builtin_fma(h * cur.cEw, pc - pW, qq);
-            qq = __builtin_fma(h * cur.cN, pc - comb(cur.zN, cur.pN), qq);
-            qq = __builtin_fma(h * cur.cNs, pc - comb(cur.zS, cur.pS), qq);
+            qq = __builtin_fma(h * cur.cN, pc - pN, qq);
+            qq = __builtin_fma(h * cNs, pc - pS, qq);
             qq = __builtin_fma(wU, pc - pp, qq);
             qq = __builtin_fma(wD, pc - pm, qq);
             bstore<CP>(pc, rpn, oo, sk);
@@ -1709,26 +1755,31 @@ hipError_t launch_pcg_apply(const Level<double> &L, const double *z, const float
     // (TPMG_CG_NT=0: never, 1: always): 1.39 vs 1.45 ms at 1024^2 x 128.
     // East / west neighbours by lane exchange where the rows are whole tiles
     // (16-level chunks only; TPMG_CG_XL=0: loads).
-    static const int ent = env_int("TPMG_CG_NT"), exl = env_int("TPMG_CG_XL");
+    static const int ent = env_int("TPMG_CG_NT"), exl = env_int("TPMG_CG_XL"), er4 = env_int("TPMG_CG_ROWS4");
     const bool nt = ent == 1 || (ent != 0 && nt_level(L));
     const bool xl = exl != 0 && (L.n & 63) == 0;
+    // four rows per workgroup with the lane exchange (TPMG_CG_ROWS4=0: one
+    // row); the same grid, n being a multiple of 64
+    const int rw = (xl && er4 != 0) ? 4 : 0;
     return with_kc(kc, [&](auto KCc) {
         constexpr int K = decltype(KCc)::value;
-        auto go = [&](auto cp, auto x) {
-            constexpr int CP = decltype(cp)::value;
+        auto go = [&](auto cp, auto x, auto rr) {
+            constexpr int CP = decltype(cp)::value, RR = decltype(rr)::value;
             constexpr bool XL = decltype(x)::value;
             if (z32)
-                hipLaunchKernelGGL((k_pcg_apply<K, float, CP, XL>), dim3(G), dim3(kStreamThreads), 0, s, L, z32,
-                                   p_old, p_new, q, sc, first, partials);
+                hipLaunchKernelGGL((k_pcg_apply<K, float, CP, XL, RR>), dim3(G), dim3(kStreamThreads), 0, s, L,
+                                   z32, p_old, p_new, q, sc, first, partials);
             else
-                hipLaunchKernelGGL((k_pcg_apply<K, double, CP, XL>), dim3(G), dim3(kStreamThreads), 0, s, L, z,
-                                   p_old, p_new, q, sc, first, partials);
+                hipLaunchKernelGGL((k_pcg_apply<K, double, CP, XL, RR>), dim3(G), dim3(kStreamThreads), 0, s, L,
+                                   z, p_old, p_new, q, sc, first, partials);
         };
+        using R0 = std::integral_constant<int, 0>;
         auto by_xl = [&](auto cp) {
             if constexpr (K == 16) {
-                if (xl) return go(cp, std::true_type());
+                if (rw == 4) return go(cp, std::true_type(), std::integral_constant<int, 4>());
+                if (xl) return go(cp, std::true_type(), R0());
             }
-            go(cp, std::false_type());
+            go(cp, std::false_type(), R0());
         };
         if (nt) by_xl(std::integral_constant<int, kNT>());
         else by_xl(std::integral_constant<int, 0>());

@@ -9,7 +9,14 @@ operands or how they walk a column, never in the arithmetic:
     TPMG_RESTRICT_XL, TPMG_CG_XL);
   - 4-level restriction chunks on small levels (TPMG_SHORT_RESTRICT_CELLS);
   - the two-column face gradient with 16-byte accesses (TPMG_FG_WIDE).
-These must agree bit for bit.  The unguarded full-chunk FP32 sweeps
+These must agree bit for bit.  The CG direction update on four rows per
+workgroup (TPMG_CG_ROWS4, neighbour rows through LDS) forms every p and q by
+the same fused multiply-adds but groups other columns in the partial (p, q)
+sums, so alpha may move by an ulp.  The iterate after two CG iterations then
+agrees to rounding (1e-13 relative); later iterates can amplify such a change
+by cancellation, so the solves to rtol 1e-9 (and the face gradient formed
+from one) agree to the accuracy of the solve (1e-8 relative), with equal
+iteration counts.  The unguarded full-chunk FP32 sweeps
 (TPMG_FULL_CHUNKS, TPMG_LAT_CELLS) compute the same expressions, but with a
 chunk's cells in one basic block the compiler contracts their FP32
 multiply-adds differently, so they agree to FP32 rounding only: measured
@@ -73,6 +80,7 @@ for p, h in H.items():
     x, info = h.solve(b64, rtol=1e-9)
     out[f"{{p}}_solve"] = x
     out[f"{{p}}_solve_iterations"] = torch.tensor([info["iterations"]])
+    out[f"{{p}}_solve_it2"], _ = h.solve(b64, rtol=1e-30, maxit=2)
 out["face_gradient"] = H["fp64"].face_gradient(vec(0), out["fp64_solve"])
 torch.cuda.synchronize()
 for h in H.values():
@@ -82,7 +90,8 @@ print("child ok", flush=True)
 """
 
 PLAIN = dict(TPMG_SWEEP_ROWS="0", TPMG_SWEEP_XL="0", TPMG_RESTRICT_XL="0", TPMG_CG_XL="0",
-             TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0", TPMG_SHORT_RESTRICT_CELLS="0", TPMG_FG_WIDE="0")
+             TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0", TPMG_SHORT_RESTRICT_CELLS="0", TPMG_FG_WIDE="0",
+             TPMG_CG_ROWS4="0")
 SETTINGS = {
     "plain": PLAIN,
     "exchange": dict(TPMG_FULL_CHUNKS="0", TPMG_LAT_CELLS="0"),
@@ -90,6 +99,10 @@ SETTINGS = {
     "default": {},
 }
 ULP32 = 2.0 ** -23
+# outputs that depend on the grouping of the CG's (p, q) partial sums, and
+# their bounds relative to the plain form
+ORDER_ONLY = {"fp64_solve_it2": 1e-13, "mixed_solve_it2": 1e-13,
+              "fp64_solve": 1e-8, "mixed_solve": 1e-8, "face_gradient": 1e-8}
 
 
 def _run(tmp_path, n, nz, name):
@@ -114,7 +127,14 @@ def test_kernel_forms_agree(tmp_path, n, nz):
         diff = [k for k in ref if not np.array_equal(got[k], ref[k])]
         print(f"[gpu] {name} vs plain (n={n}, nz={nz}): {len(ref)} outputs, differing {json.dumps(diff)}",
               flush=True)
-        if name != "default" or nz % 8:
+        fp32_forms = name == "default" and nz % 8 == 0
+        for k in [k for k in diff if k in ORDER_ONLY and not (fp32_forms and k.startswith("mixed_"))]:
+            e = rel_err(got[k], ref[k])
+            print(f"[gpu]   {k}: relative difference {e:.2e} (grouping of the (p, q) sums, bound "
+                  f"{ORDER_ONLY[k]:.0e})", flush=True)
+            assert e <= ORDER_ONLY[k], (k, e)
+            diff.remove(k)
+        if not fp32_forms:
             assert not diff, diff
             continue
         # unguarded FP32 sweeps: FP32 outputs within the FP32 bound of the
