@@ -1106,7 +1106,13 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
 // b is in the level's storage, or level-major when b_level is set.  With
 // xout, x is also written there in level-major order (the end of a solve:
 // the copy of the iterate to the caller rides on this pass).
-template <int KC>
+// The stencil sum is formed by explicit fused multiply-adds in a fixed order,
+// so both forms round alike.  XL (rows of whole tiles): east / west x from
+// the neighbouring lanes, as in k_pcg_apply (1024^2 x 128: 1.427 vs 1.444 ms;
+// passing the north / south rows through LDS on four-row workgroups, as
+// k_pcg_apply does, gained nothing more here: without a lookahead this
+// kernel waits on each level's loads, not on their number).
+template <int KC, bool XL = false>
 __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, const double *__restrict__ x,
                                                              const double *__restrict__ b, int b_level,
                                                              double *__restrict__ r,
@@ -1116,13 +1122,15 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
     int col, k0;
     bool active;
     stream_coords<KC>(L, col, k0, active);
-    const int nz = L.nz;
+    const int nz = L.nz, lane = threadIdx.x & 63;
     const StencilRows<double> R(L, col);
     const size_t fbytes = (size_t)nz * L.plane * 8;
     const Rsrc rx = make_rsrc(x, fbytes), rb = make_rsrc(b, fbytes), rr = make_rsrc(r, r ? fbytes : 0);
     const Rsrc rxo = make_rsrc(xout, xout ? fbytes : 0);
     const unsigned oo = active ? R.oc : 0xFFFFFFFFu, ol = active ? (unsigned)col * 8u : 0xFFFFFFFFu;
     const unsigned lstride = (unsigned)L.plane * 8u;
+    // the value across the tile edge (lanes 0 and 63) for the lane exchange
+    const unsigned ox = lane == 0 ? R.ow : (lane == 63 ? R.oe : R.oc);
     double xm = 0, wD = 0;
     if (k0 > 0) {
         const unsigned sm = (unsigned)(k0 - 1) * R.pstride;
@@ -1139,11 +1147,26 @@ __global__ __launch_bounds__(kStreamThreads) void k_residual(Level<double> L, co
             const double xp = (k + 1 < nz) ? bload(double(), rx, R.oc, sk + R.pstride) : 0.0;
             const double h = L.wh[k];
             const double wU = L.wz[k] * bload(double(), R.rU, R.oc, sk);
-            const double hx = L.mu[k] * xc + h * bload(double(), R.rE, R.oc, sk) * (xc - bload(double(), rx, R.oe, sk)) +
-                              h * bload(double(), R.rE, R.ow, sk) * (xc - bload(double(), rx, R.ow, sk)) +
-                              h * bload(double(), R.rN, R.oc, sk) * (xc - bload(double(), rx, R.on, sk)) +
-                              h * bload(double(), R.rN, R.os, sk) * (xc - bload(double(), rx, R.os, sk)) +
-                              wU * (xc - xp) + wD * (xc - xm);
+            const double cE = bload(double(), R.rE, R.oc, sk), cEw = bload(double(), R.rE, R.ow, sk);
+            const double cN = bload(double(), R.rN, R.oc, sk);
+            double xE, xW;
+            if constexpr (XL) {
+                const double xx = bload(double(), rx, ox, sk);
+                xE = lane_from_next(xx, xc);
+                xW = lane_from_prev(xx, xc);
+            } else {
+                xE = bload(double(), rx, R.oe, sk);
+                xW = bload(double(), rx, R.ow, sk);
+            }
+            const double xN = bload(double(), rx, R.on, sk), xS = bload(double(), rx, R.os, sk);
+            const double cNs = bload(double(), R.rN, R.os, sk);
+            double hx = L.mu[k] * xc;
+            hx = __builtin_fma(h * cE, xc - xE, hx);
+            hx = __builtin_fma(h * cEw, xc - xW, hx);
+            hx = __builtin_fma(h * cN, xc - xN, hx);
+            hx = __builtin_fma(h * cNs, xc - xS, hx);
+            hx = __builtin_fma(wU, xc - xp, hx);
+            hx = __builtin_fma(wD, xc - xm, hx);
             const double bv = b_level ? bload(double(), rb, ol, (unsigned)k * lstride) : bload(double(), rb, R.oc, sk);
             const double rv = bv - hx;
             if (r) bstore(rv, rr, oo, sk);
@@ -1793,9 +1816,20 @@ hipError_t launch_residual(const Level<double> &L, const double *x, const double
     const int kc = stream_kc(L.nz >= 64 && L.plane >= 256 * 256 ? 64 : 16);
     const int G = stream_grid(L, kc);
     *nblocks_out = G;
+    // lane exchange where the rows are whole tiles (TPMG_CG_XL=0: loads)
+    static const int exl = env_int("TPMG_CG_XL");
+    const bool xl = exl != 0 && (L.n & 63) == 0;
     return with_kc(kc, [&](auto KCc) {
-        hipLaunchKernelGGL((k_residual<decltype(KCc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b, b_level,
-                           r, xout, partials);
+        constexpr int K = decltype(KCc)::value;
+        auto go = [&](auto xlc) {
+            hipLaunchKernelGGL((k_residual<K, decltype(xlc)::value>), dim3(G), dim3(kStreamThreads), 0, s, L, x, b,
+                               b_level, r, xout, partials);
+        };
+        bool done = false;
+        if constexpr (K == 16 || K == 64) {
+            if (xl) go(std::true_type()), done = true;
+        }
+        if (!done) go(std::false_type());
         return hipGetLastError();
     });
 }
