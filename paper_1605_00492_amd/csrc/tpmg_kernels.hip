@@ -1066,9 +1066,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_pcg_apply(Level<double> L, c
             }
             double pN, pS, cNs;
             if constexpr (R4) {
-                // double-buffered by level: a wavefront writes slot t & 1 of
-                // level k + 1 only after the barrier of level k, which every
-                // wavefront reaches after reading that slot for level k - 1
+                // double-buffered by level: slot t & 1 serves level k and is
+                // written again (for level k + 2) only after the barrier of
+                // level k + 1, which every wavefront reaches only after
+                // reading the slot for level k
                 __shared__ double xp[2][R4 ? RW : 1][64], xc[2][R4 ? RW : 1][64];
                 const int sl = t & 1;
                 xp[sl][wv][lane] = pc;
